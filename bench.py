@@ -1,0 +1,154 @@
+"""Throughput of the D3Q19 BGK + implicit-IBM time step on one MI355X.
+
+A step is one pass of the whole hot path over the lattice: marker
+kinematics, delta interpolation, the no-slip solve, spreading, the fused
+collide-stream with Guo forcing and the force/coefficient reduction.  The
+default workload is the clap & fling pair (chord 20, aspect 5) in a
+256x192x192 box at Re = 100, J = 0.01, f = 0.25, FP32 storage, synthetic
+seeded initial noise.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload cf|large|plate]
+                    [--storage fp32|fp16|bf16] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as WL  # noqa: E402
+
+METRIC = "MLUPS (D3Q19+IBM) & fraction of HBM roofline; sweep p50/p99 latency"
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E peak
+
+
+def workload(name):
+    if name == "cf":
+        bx, wg, ph = WL.clap_fling_case(nx=256, ny=192, nz=192, chord=20.0, re=100.0, j=0.01, f=0.25)
+        return "clap_fling_256x192x192", bx, wg, ph
+    if name == "large":
+        bx, wg, ph = WL.clap_fling_case(nx=512, ny=384, nz=384, chord=40.0, re=150.0, j=0.01, f=0.25)
+        return "clap_fling_512x384x384", bx, wg, ph
+    if name == "plate":
+        bx, wg, ph = WL.plate_case()
+        return "plate_64x32x32", bx, wg, ph
+    raise SystemExit(f"unknown workload {name}")
+
+
+def initial_velocity(bx, ph, u_inf, seed=0):
+    u0 = WL.velocity_noise((bx["nz"], bx["ny"], bx["nx"]), seed)
+    u0[0] += u_inf
+    return u0
+
+
+def cpu_baseline(bx, wg, ph, u0, steps):
+    """The FP64 oracle on the host, single-threaded, over `steps` steps of
+    the same workload (setup excluded)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import params
+    from oracle.sim import Sim
+
+    ob, ow = params.complete_case(bx, wg, ph)
+    with threadpool_limits(limits=1):
+        s = Sim(ob, ow, u0=u0)
+        t0 = time.perf_counter()
+        s.run(steps)
+        dt = time.perf_counter() - t0
+    n = bx["nx"] * bx["ny"] * bx["nz"]
+    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
+                sample=f"{steps} full step(s) of the same workload "
+                       f"({bx['nx']}x{bx['ny']}x{bx['nz']}, all markers), FP64 NumPy, "
+                       f"{dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="cf")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
+              "has no multi-GPU path in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2102_01305_amd.solver import Solver, complete_case
+
+    name, bx, wg, ph = workload(args.workload)
+    gb, gw = complete_case(bx, wg, ph)
+    u0 = initial_velocity(bx, ph, gb["u_in"][0])
+    print(f"[bench] {name} storage={args.storage} tau={gb['tau']:.4f} steps={args.steps} "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    s = Solver(gb, gw, storage=args.storage, history_steps=max(args.steps + args.warmup, 16))
+    s.init_fields(u=u0)
+    N = bx["nx"] * bx["ny"] * bx["nz"]
+
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    # timed region: K whole steps, bracketed by device synchronisation;
+    # collide launches are bracketed by HIP events on the solver's stream
+    s.enable_timing(True)
+    s.read_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = s.read_timing()
+    s.enable_timing(False)
+    # sanity: the solve is still finite
+    f = s.forces(s.step_count - 1, 1)
+    if not np.all(np.isfinite(f)):
+        raise SystemExit("non-finite forces after the timed run")
+    s.close()
+
+    mlups = N * args.steps / dt / 1e6
+    bpc = 2 * 19 * (4 if args.storage == "fp32" else 2)
+    k6_ms = tim["collide_ms"] / max(tim["collide_launches"], 1)
+    achieved = bpc * N / (k6_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "cells": N, "storage": args.storage,
+                   "re": ph.get("re"), "j": ph.get("j"), "f": ph.get("f"),
+                   "wings": len(wg)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_collide", "kernel_ms": round(k6_ms, 5),
+                     "bytes_per_cell": bpc,
+                     "marker_ms_per_step": round(tim["marker_ms"] / max(args.steps, 1), 5)},
+        "hbm_frac_whole_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(bx, wg, ph, u0, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,906 @@
+// Host side of libibmlbm: configuration checks, workspace carving, marker
+// geometry, launch order of the time step, and read-back.  See ibmlbm.h for
+// the contract of every entry point.
+#include "../../include/ibmlbm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ibmk;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Region {
+  size_t off = 0, bytes = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct LatticeLayout {
+  int es = 4;        // bytes per stored value
+  int px = 0;
+  long long ps = 0;
+  size_t N = 0;
+  int tnx = 0, tny = 0, tnz = 0;
+  int nxc = 0, nblocks = 0;
+  Region fA, fB, du, stamps, mass_part, diag;
+  size_t end = 0;
+};
+
+struct WingGeom {
+  int np = 0;
+  double ds = 0.0;                 // perimeter / np
+  std::vector<double> ref;         // np x 2, relative to the pivot
+  double rmax = 0.0;
+};
+
+struct MarkerLayout {
+  Region ref, G, Minv, X, U, B, rhoB, duB, fpart, counters, hist;
+  size_t end = 0;
+  int m_total = 0, layers = 0;
+};
+
+}  // namespace
+
+struct ibmlbm_s {
+  ibmlbm_config cfg{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  LatticeLayout L;
+  Geo geo{};
+  Phys phys{};
+  bool cur_is_A = true;
+  bool initialized = false;
+  long long step = 0;
+  // markers
+  int nw = 0;
+  ibmlbm_wing wings[kMaxWings]{};
+  WingDev wd[kMaxWings]{};
+  std::vector<WingGeom> geom;
+  MarkerLayout M;
+  bool markers_valid = false;       // marker outputs of a completed step exist
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;       // pairs: start, stop
+  std::vector<int> ev_kind;         // 0 = collide, 1 = markers
+  size_t ev_used = 0;
+  double acc_collide_ms = 0.0, acc_marker_ms = 0.0;
+  long long acc_collide_n = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(ibmlbm_t h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(h, expr)                                                                  \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail((h), IBMLBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+template <class T>
+T* at(ibmlbm_t h, const Region& r) {
+  return reinterpret_cast<T*>(h->ws + r.off);
+}
+
+void* cur_state(ibmlbm_t h) { return h->ws + (h->cur_is_A ? h->L.fA.off : h->L.fB.off); }
+void* next_state(ibmlbm_t h) { return h->ws + (h->cur_is_A ? h->L.fB.off : h->L.fA.off); }
+
+int validate_config(const ibmlbm_config* c, std::string& why) {
+  char b[256];
+  if (!c) { why = "null config"; return IBMLBM_EINVAL; }
+  if (c->nx < 4 || c->ny < 4 || c->nz < 4) { why = "nx, ny, nz must each be >= 4"; return IBMLBM_EINVAL; }
+  if ((long long)c->nx * c->ny * c->nz > (1LL << 34)) { why = "box too large"; return IBMLBM_EINVAL; }
+  for (int f = 0; f < 6; ++f) {
+    if (c->bc[f] < 0 || c->bc[f] > 3) { snprintf(b, sizeof b, "bc[%d] unknown", f); why = b; return IBMLBM_EINVAL; }
+    if (f >= 2 && (c->bc[f] == IBMLBM_BC_VELOCITY || c->bc[f] == IBMLBM_BC_PRESSURE)) {
+      why = "VELOCITY/PRESSURE faces are supported on x faces only";
+      return IBMLBM_EINVAL;
+    }
+  }
+  for (int a = 0; a < 3; ++a)
+    if ((c->bc[2 * a] == IBMLBM_BC_PERIODIC) != (c->bc[2 * a + 1] == IBMLBM_BC_PERIODIC)) {
+      snprintf(b, sizeof b, "axis %d: PERIODIC must be set on both faces", a);
+      why = b;
+      return IBMLBM_EINVAL;
+    }
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau)) { why = "tau must be finite and > 0.5"; return IBMLBM_EINVAL; }
+  if (c->storage < 0 || c->storage > 2) { why = "unknown storage"; return IBMLBM_EINVAL; }
+  if (c->check_interval < 0) { why = "check_interval must be >= 0"; return IBMLBM_EINVAL; }
+  if (c->history_steps < 1) { why = "history_steps must be >= 1"; return IBMLBM_EINVAL; }
+  if (!(c->rho_out > 0.0)) { why = "rho_out must be > 0"; return IBMLBM_EINVAL; }
+  if (!(c->u_ref > 0.0) || !(c->area_ref > 0.0)) { why = "u_ref and area_ref must be > 0"; return IBMLBM_EINVAL; }
+  return IBMLBM_OK;
+}
+
+LatticeLayout lattice_layout(const ibmlbm_config* c) {
+  LatticeLayout L;
+  L.es = c->storage == IBMLBM_FP32 ? 4 : 2;
+  const int line = 128 / L.es;
+  L.px = ((c->nx + 2 + line - 1) / line) * line;
+  L.ps = ((long long)c->ny * c->nz + 1) * L.px;
+  L.N = (size_t)c->nx * c->ny * c->nz;
+  L.tnx = (c->nx + kTile - 1) / kTile;
+  L.tny = (c->ny + kTile - 1) / kTile;
+  L.tnz = (c->nz + kTile - 1) / kTile;
+  L.nxc = (c->nx + kBlockX - 1) / kBlockX;
+  L.nblocks = L.nxc * ((c->ny * c->nz + kBlockRows - 1) / kBlockRows);
+  size_t o = 0;
+  auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + bytes); };
+  take(L.fA, (size_t)kQ * L.ps * L.es);
+  take(L.fB, (size_t)kQ * L.ps * L.es);
+  take(L.du, 3 * L.N * sizeof(float));
+  take(L.stamps, (size_t)L.tnx * L.tny * L.tnz * sizeof(int));
+  take(L.mass_part, (size_t)L.nblocks * sizeof(double));
+  take(L.diag, 64);
+  L.end = o;
+  return L;
+}
+
+// ----------------------------------------------------------- host geometry --
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton iteration on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) {
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        break;
+      }
+      x[i] = z;
+      w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+  }
+}
+
+struct Arc {
+  double a, b;
+  std::vector<double> gx, gw;
+  int panels = 512;
+  Arc(double a_, double b_) : a(a_), b(b_) { gauss_legendre(16, gx, gw); }
+  double speed(double t) const { return std::hypot(a * std::sin(t), b * std::cos(t)); }
+  // arc length from 0 to phi (phi in [0, 2 pi]) by composite Gauss-Legendre
+  double length(double phi) const {
+    const double h = 2.0 * M_PI / panels;
+    double s = 0.0;
+    int full = (int)std::floor(phi / h);
+    if (full > panels) full = panels;
+    for (int k = 0; k <= full; ++k) {
+      const double lo = k * h;
+      const double hi = std::min(phi, (k + 1) * h);
+      if (hi <= lo) break;
+      const double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
+      double acc = 0.0;
+      for (size_t j = 0; j < gx.size(); ++j) acc += gw[j] * speed(c + r * gx[j]);
+      s += r * acc;
+    }
+    return s;
+  }
+};
+
+// Equal-arc-length markers on the ellipse of one foil; the first at the
+// trailing edge (local (a, 0)), counter-clockwise; coordinates relative to
+// the pivot on the chord (pivot_frac 0 = LE at (-a, 0), 1 = TE).
+int wing_geometry(const ibmlbm_wing& w, WingGeom& g, std::string& why) {
+  if (!(w.chord > 0.0) || !(w.thickness > 0.0) || w.thickness > w.chord || !(w.ds > 0.0)) {
+    why = "foil needs chord > 0, 0 < thickness <= chord and ds > 0";
+    return IBMLBM_EINVAL;
+  }
+  const double a = 0.5 * w.chord, b = 0.5 * w.thickness;
+  Arc arc(a, b);
+  const double P = arc.length(2.0 * M_PI);
+  const int n = std::max(3, (int)std::lround(P / w.ds));
+  if (n > kMaxPerim) {
+    why = "too many perimeter markers (max 128): reduce chord or raise ds";
+    return IBMLBM_EINVAL;
+  }
+  g.np = n;
+  g.ds = P / n;
+  g.ref.assign(2 * n, 0.0);
+  const double xp = -a + 2.0 * a * w.pivot_frac;
+  g.rmax = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double target = j * g.ds;
+    double phi = 2.0 * M_PI * target / P;
+    for (int it = 0; it < 60; ++it) {
+      const double d = (arc.length(phi) - target) / arc.speed(phi);
+      phi -= d;
+      if (std::fabs(d) < 1e-15) break;
+    }
+    const double rx = a * std::cos(phi) - xp, ry = b * std::sin(phi);
+    g.ref[2 * j] = rx;
+    g.ref[2 * j + 1] = ry;
+    g.rmax = std::max(g.rmax, std::hypot(rx, ry));
+  }
+  return IBMLBM_OK;
+}
+
+double delta_h(double r) {
+  r = std::fabs(r);
+  return r <= 2.0 ? 0.25 * (1.0 + std::cos(0.5 * M_PI * r)) : 0.0;
+}
+
+// a(p, q) = sum_j delta(j - p) delta(j - q), periodic of length n if per
+double a1_h(double p, double q, int n, bool per) {
+  const double fb = std::floor(p) - 1.0;
+  double s = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    double r = fb + k - q;
+    if (per) r -= n * std::rint(r / n);
+    s += delta_h(fb + k - p) * delta_h(r);
+  }
+  return s;
+}
+
+void pose_h(const ibmlbm_wing& w, double t, double& th, double& hx, double& hy) {
+  double al = w.alpha_mean;
+  if (w.alpha_shape == IBMLBM_ALPHA_SIN) {
+    al = w.alpha_mean + w.alpha_amp * std::sin(2.0 * M_PI * t / w.period_steps + w.phase);
+  } else if (w.alpha_shape == IBMLBM_ALPHA_ABS_SIN) {
+    const double psi = t / w.period_steps + w.phase / (2.0 * M_PI);
+    const double h = psi - std::floor(2.0 * psi) / 2.0;
+    al = w.alpha_mean + w.alpha_amp * std::sin(2.0 * M_PI * h);
+  }
+  th = w.theta0 + w.sense * al;
+  hx = w.hinge[0];
+  hy = w.hinge[1];
+  if (w.trans_amp != 0.0) {
+    const double A = w.trans_amp * std::cos(2.0 * M_PI * t / w.period_steps + w.phase);
+    hx += A * std::cos(w.trans_angle);
+    hy += A * std::sin(w.trans_angle);
+  }
+}
+
+void perimeter_xy(const ibmlbm_wing& w, const WingGeom& g, double t, std::vector<double>& xy) {
+  double th, hx, hy;
+  pose_h(w, t, th, hx, hy);
+  const double c = std::cos(th), s = std::sin(th);
+  xy.resize(2 * g.np);
+  for (int p = 0; p < g.np; ++p) {
+    const double px = g.ref[2 * p], py = g.ref[2 * p + 1];
+    xy[2 * p] = hx + (c * px - s * py);
+    xy[2 * p + 1] = hy + (s * px + c * py);
+  }
+}
+
+// Smallest Cholesky pivot of the perimeter block relative to its largest
+// diagonal entry; <= 0 means not positive definite.
+double perimeter_conditioning(const std::vector<double>& xy, int n, const ibmlbm_config& c) {
+  std::vector<double> M((size_t)n * n);
+  const bool px = c.bc[0] == IBMLBM_BC_PERIODIC, py = c.bc[2] == IBMLBM_BC_PERIODIC;
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      M[(size_t)p * n + q] = a1_h(xy[2 * p], xy[2 * q], c.nx, px) * a1_h(xy[2 * p + 1], xy[2 * q + 1], c.ny, py);
+  double dmax = 0.0;
+  for (int p = 0; p < n; ++p) dmax = std::max(dmax, M[(size_t)p * n + p]);
+  double pmin = 1e300;
+  for (int k = 0; k < n; ++k) {
+    double d = M[(size_t)k * n + k];
+    for (int j = 0; j < k; ++j) d -= M[(size_t)k * n + j] * M[(size_t)k * n + j];
+    if (!(d > 0.0)) return -1.0;
+    pmin = std::min(pmin, d);
+    const double l = std::sqrt(d);
+    M[(size_t)k * n + k] = l;
+    for (int i = k + 1; i < n; ++i) {
+      double v = M[(size_t)i * n + k];
+      for (int j = 0; j < k; ++j) v -= M[(size_t)i * n + j] * M[(size_t)k * n + j];
+      M[(size_t)i * n + k] = v / l;
+    }
+  }
+  return pmin / dmax;
+}
+
+// Row of the pseudo-inverse of the circulant span factor M_z, with
+// M_z[s][s'] = a(s + 1/2, s' + 1/2) on a periodic axis of ns cells.  The
+// cosine kernel makes the alternating mode exactly null; eigenvalues below
+// 1e-12 of the largest are dropped (minimum-norm solution).
+void span_pinv_row(int ns, std::vector<double>& G) {
+  std::vector<double> r(ns);
+  for (int j = 0; j < ns; ++j) r[j] = a1_h(0.5, j + 0.5, ns, true);
+  std::vector<double> lam(ns);
+  double lmax = 0.0;
+  for (int k = 0; k < ns; ++k) {
+    double s = 0.0;
+    for (int j = 0; j < ns; ++j) s += r[j] * std::cos(2.0 * M_PI * (double)((long long)j * k % ns) / ns);
+    lam[k] = s;
+    lmax = std::max(lmax, std::fabs(s));
+  }
+  G.assign(ns, 0.0);
+  for (int j = 0; j < ns; ++j) {
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) {
+      if (std::fabs(lam[k]) <= 1e-12 * lmax) continue;
+      s += std::cos(2.0 * M_PI * (double)((long long)j * k % ns) / ns) / lam[k];
+    }
+    G[j] = s / ns;
+  }
+}
+
+int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vector<WingGeom>& geo,
+                std::string& why) {
+  char b[256];
+  if (nw < 0 || nw > kMaxWings) { why = "n_wings must be in 0..8"; return IBMLBM_EINVAL; }
+  if (nw > 0 && !w) { why = "null wings"; return IBMLBM_EINVAL; }
+  geo.assign(nw, WingGeom{});
+  if (nw > 0 && c.bc[4] != IBMLBM_BC_PERIODIC) {
+    why = "foils are extruded over the span: z must be periodic";
+    return IBMLBM_EINVAL;
+  }
+  for (int k = 0; k < nw; ++k) {
+    const ibmlbm_wing& x = w[k];
+    if (x.sense != 1.0 && x.sense != -1.0) { why = "sense must be +1 or -1"; return IBMLBM_EINVAL; }
+    if (x.alpha_shape < 0 || x.alpha_shape > 2) { why = "unknown alpha shape"; return IBMLBM_EINVAL; }
+    if ((x.alpha_shape != IBMLBM_ALPHA_CONST || x.trans_amp != 0.0) && !(x.period_steps > 0.0)) {
+      why = "moving foils need period_steps > 0";
+      return IBMLBM_EINVAL;
+    }
+    if (x.pivot_frac < 0.0 || x.pivot_frac > 1.0) { why = "pivot_frac must be in [0, 1]"; return IBMLBM_EINVAL; }
+    int rc = wing_geometry(x, geo[k], why);
+    if (rc) return rc;
+    // supports on non-periodic axes: every node floor(X)-1 .. floor(X)+2 inside
+    const double reach = geo[k].rmax + std::fabs(x.trans_amp);
+    if (c.bc[0] != IBMLBM_BC_PERIODIC &&
+        (x.hinge[0] - reach < 1.0 || x.hinge[0] + reach >= c.nx - 2.0)) {
+      snprintf(b, sizeof b, "foil %d: marker supports may leave the box along x", k);
+      why = b;
+      return IBMLBM_EINVAL;
+    }
+    if (c.bc[2] != IBMLBM_BC_PERIODIC &&
+        (x.hinge[1] - reach < 1.0 || x.hinge[1] + reach >= c.ny - 2.0)) {
+      snprintf(b, sizeof b, "foil %d: marker supports may leave the box along y", k);
+      why = b;
+      return IBMLBM_EINVAL;
+    }
+  }
+  // sampled over one period of the slowest foil: separation of supports and
+  // conditioning of every perimeter block
+  double T = 1.0;
+  for (int k = 0; k < nw; ++k)
+    if (w[k].alpha_shape != IBMLBM_ALPHA_CONST || w[k].trans_amp != 0.0) T = std::max(T, w[k].period_steps);
+  const int samples = 97;
+  std::vector<std::vector<double>> xy(nw);
+  for (int sidx = 0; sidx < samples; ++sidx) {
+    const double t = T * sidx / (samples - 1);
+    for (int k = 0; k < nw; ++k) {
+      perimeter_xy(w[k], geo[k], t, xy[k]);
+      if (perimeter_conditioning(xy[k], geo[k].np, c) < 1e-9) {
+        snprintf(b, sizeof b, "foil %d: perimeter system (Eq. 18) is singular; raise ds", k);
+        why = b;
+        return IBMLBM_EINVAL;
+      }
+    }
+    for (int k = 0; k < nw; ++k)
+      for (int l = k + 1; l < nw; ++l)
+        for (int p = 0; p < geo[k].np; ++p)
+          for (int q = 0; q < geo[l].np; ++q) {
+            const double dx = std::fabs(xy[k][2 * p] - xy[l][2 * q]);
+            const double dy = std::fabs(xy[k][2 * p + 1] - xy[l][2 * q + 1]);
+            if (std::max(dx, dy) < 4.5) {
+              snprintf(b, sizeof b, "foils %d and %d come within the delta support of each other", k, l);
+              why = b;
+              return IBMLBM_EINVAL;
+            }
+          }
+  }
+  return IBMLBM_OK;
+}
+
+MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<WingGeom>& geo,
+                           size_t start) {
+  MarkerLayout M;
+  size_t nref = 0, nG = 0, nMinv = 0;
+  for (int k = 0; k < nw; ++k) {
+    nref += 2 * geo[k].np;
+    nG += c.nz;
+    nMinv += (size_t)geo[k].np * geo[k].np;
+    M.m_total += geo[k].np * c.nz;
+    M.layers += c.nz;
+  }
+  size_t o = align256(start);
+  auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + std::max<size_t>(bytes, 8)); };
+  const size_t m = M.m_total;
+  take(M.ref, nref * 8);
+  take(M.G, nG * 8);
+  take(M.Minv, nMinv * 8);
+  take(M.X, 3 * m * 8);
+  take(M.U, 3 * m * 8);
+  take(M.B, 3 * m * 8);
+  take(M.rhoB, m * 8);
+  take(M.duB, 3 * m * 8);
+  take(M.fpart, 4 * (size_t)M.layers * 8);
+  take(M.counters, (size_t)std::max(nw, 1) * 4);
+  take(M.hist, (size_t)c.history_steps * std::max(nw, 1) * 8 * 8);
+  M.end = o;
+  return M;
+}
+
+void fill_phys(ibmlbm_t h) {
+  const ibmlbm_config& c = h->cfg;
+  h->phys.omega = (float)(1.0 / c.tau);
+  h->phys.guo_k = (float)(1.0 - 0.5 / c.tau);
+  for (int d = 0; d < 3; ++d) {
+    h->phys.fb[d] = (float)c.body_force[d];
+    h->phys.u_in[d] = (float)c.u_in[d];
+  }
+  h->phys.rho_out = (float)c.rho_out;
+}
+
+int record_event(ibmlbm_t h, int kind, bool start) {
+  if (!h->timing) return IBMLBM_OK;
+  if (start) {
+    if (h->ev_used + 2 > h->ev.size()) {
+      // pool full: fold the recorded pairs into the sums first
+      HIP_TRY(h, hipStreamSynchronize(h->stream));
+      for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+        if (h->ev_kind[k / 2] == 0) { h->acc_collide_ms += ms; h->acc_collide_n++; }
+        else h->acc_marker_ms += ms;
+      }
+      h->ev_used = 0;
+    }
+    h->ev_kind[h->ev_used / 2] = kind;
+  }
+  HIP_TRY(h, hipEventRecord(h->ev[h->ev_used], h->stream));
+  h->ev_used++;
+  return IBMLBM_OK;
+}
+
+}  // namespace
+
+// ================================================================== C ABI ==
+extern "C" {
+
+size_t ibmlbm_workspace_bytes(const ibmlbm_config* cfg, int32_t n_wings, const ibmlbm_wing* wings) {
+  std::string why;
+  if (validate_config(cfg, why)) { g_err = why; return 0; }
+  LatticeLayout L = lattice_layout(cfg);
+  if (n_wings == 0) return L.end;
+  std::vector<WingGeom> geo;
+  if (check_wings(*cfg, n_wings, wings, geo, why)) { g_err = why; return 0; }
+  return marker_layout(*cfg, n_wings, geo, L.end).end;
+}
+
+int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                  ibmlbm_t* out) {
+  if (!out) return fail(nullptr, IBMLBM_EINVAL, "null output handle");
+  *out = nullptr;
+  std::string why;
+  int rc = validate_config(cfg, why);
+  if (rc) return fail(nullptr, rc, "%s", why.c_str());
+  if (!dev_workspace) return fail(nullptr, IBMLBM_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(nullptr, IBMLBM_EINVAL, "workspace must be 256-byte aligned");
+  LatticeLayout L = lattice_layout(cfg);
+  if (bytes < L.end) return fail(nullptr, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, L.end);
+  ibmlbm_t h = new ibmlbm_s();
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(dev_workspace);
+  h->ws_bytes = bytes;
+  h->L = L;
+  h->geo.nx = cfg->nx;
+  h->geo.ny = cfg->ny;
+  h->geo.nz = cfg->nz;
+  h->geo.px = L.px;
+  h->geo.ps = L.ps;
+  h->geo.yper = cfg->bc[2] == IBMLBM_BC_PERIODIC;
+  h->geo.zper = cfg->bc[4] == IBMLBM_BC_PERIODIC;
+  h->geo.bclo = cfg->bc[0];
+  h->geo.bchi = cfg->bc[1];
+  fill_phys(h);
+  hipError_t e = hipMemsetAsync(h->ws + L.du.off, 0, L.du.bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.stamps.off, 0, L.stamps.bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    int r = fail(nullptr, IBMLBM_EDEVICE, "workspace clear failed: %s", hipGetErrorString(e));
+    delete h;
+    return r;
+  }
+  *out = h;
+  return IBMLBM_OK;
+}
+
+int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const double* fdist, int64_t step0) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (step0 < 0) return fail(h, IBMLBM_EINVAL, "step0 must be >= 0");
+  const LatticeLayout& L = h->L;
+  const size_t N = L.N;
+  h->cur_is_A = true;
+  void* dst = h->ws + L.fA.off;
+  if (fdist) {
+    // pack f_i - w_i into the padded layout on the host
+    const double w[kQ] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    std::vector<unsigned char> host((size_t)kQ * L.ps * L.es, 0);
+    const int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
+    for (int q = 0; q < kQ; ++q)
+      for (int z = 0; z < nz; ++z)
+        for (int y = 0; y < ny; ++y)
+          for (int x = 0; x < nx; ++x) {
+            const size_t cell = ((size_t)z * ny + y) * nx + x;
+            const float v = (float)(fdist[(size_t)q * N + cell] - w[q]);
+            const size_t idx = (size_t)q * L.ps + ((size_t)(z * ny + y) + 1) * L.px + x;
+            if (L.es == 4) {
+              std::memcpy(&host[idx * 4], &v, 4);
+            } else if (h->cfg.storage == IBMLBM_FP16_DEV) {
+              _Float16 hv = (_Float16)v;
+              std::memcpy(&host[idx * 2], &hv, 2);
+            } else {
+              uint32_t u32;
+              std::memcpy(&u32, &v, 4);
+              u32 += 0x7fffu + ((u32 >> 16) & 1u);
+              const uint16_t b16 = (uint16_t)(u32 >> 16);
+              std::memcpy(&host[idx * 2], &b16, 2);
+            }
+          }
+    HIP_TRY(h, hipMemcpyAsync(dst, host.data(), host.size(), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  } else {
+    // stage FP64 rho and u in the other state buffer (free between steps)
+    double* stage = at<double>(h, L.fB);
+    if ((rho ? N : 0) * 8 + (u ? 3 * N : 0) * 8 > L.fB.bytes)
+      return fail(h, IBMLBM_ENOMEM, "staging area too small");
+    double* drho = rho ? stage : nullptr;
+    double* du = u ? stage + (rho ? N : 0) : nullptr;
+    if (rho) HIP_TRY(h, hipMemcpyAsync(drho, rho, N * 8, hipMemcpyHostToDevice, h->stream));
+    if (u) HIP_TRY(h, hipMemcpyAsync(du, u, 3 * N * 8, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, launch_init_eq(h->cfg.storage, h->geo, drho, du, dst, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+  }
+  HIP_TRY(h, launch_ghost(h->cfg.storage, h->geo, h->phys, dst, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->ws + L.stamps.off, 0, L.stamps.bytes, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->ws + L.du.off, 0, L.du.bytes, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->step = step0;
+  h->initialized = true;
+  h->markers_valid = false;
+  return IBMLBM_OK;
+}
+
+int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  std::string why;
+  std::vector<WingGeom> geo;
+  int rc = check_wings(h->cfg, n_wings, wings, geo, why);
+  if (rc) return fail(h, rc, "%s", why.c_str());
+  MarkerLayout M = marker_layout(h->cfg, n_wings, geo, h->L.end);
+  if (n_wings > 0 && M.end > h->ws_bytes)
+    return fail(h, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed for the markers", h->ws_bytes, M.end);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->nw = n_wings;
+  h->geom = geo;
+  h->M = M;
+  h->markers_valid = false;
+  if (n_wings == 0) return IBMLBM_OK;
+  std::vector<double> ref, G;
+  int moff = 0, roff = 0, goff = 0, moff2 = 0, loff = 0;
+  for (int k = 0; k < n_wings; ++k) {
+    const ibmlbm_wing& w = wings[k];
+    h->wings[k] = w;
+    WingDev& d = h->wd[k];
+    d.np = geo[k].np;
+    d.ns = h->cfg.nz;
+    d.moff = moff;
+    d.ref_off = roff;
+    d.g_off = goff;
+    d.minv_off = moff2;
+    d.layer_off = loff;
+    d.shape = w.alpha_shape;
+    d.hinge0[0] = w.hinge[0];
+    d.hinge0[1] = w.hinge[1];
+    d.theta0 = w.theta0;
+    d.sense = w.sense;
+    d.mean = w.alpha_mean;
+    d.amp = w.alpha_amp;
+    d.period = w.period_steps > 0.0 ? w.period_steps : 1.0;
+    d.phase = w.phase;
+    d.tamp = w.trans_amp;
+    d.tang = w.trans_angle;
+    d.dA = geo[k].ds * 1.0;
+    d.chord = w.chord;
+    ref.insert(ref.end(), geo[k].ref.begin(), geo[k].ref.end());
+    std::vector<double> g;
+    span_pinv_row(h->cfg.nz, g);
+    G.insert(G.end(), g.begin(), g.end());
+    moff += d.np * d.ns;
+    roff += 2 * d.np;
+    goff += d.ns;
+    moff2 += d.np * d.np;
+    loff += d.ns;
+  }
+  HIP_TRY(h, hipMemcpyAsync(h->ws + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->ws + M.G.off, G.data(), G.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->ws + M.counters.off, 0, M.counters.bytes, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->ws + M.hist.off, 0, M.hist.bytes, h->stream));
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return IBMLBM_OK;
+}
+
+int ibmlbm_step(ibmlbm_t h, int32_t n) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (!h->initialized) return fail(h, IBMLBM_ESTATE, "init_fields must be called before step");
+  if (n < 0) return fail(h, IBMLBM_EINVAL, "negative step count");
+  const LatticeLayout& L = h->L;
+  const ibmlbm_config& c = h->cfg;
+  const bool force = c.body_force[0] != 0.0 || c.body_force[1] != 0.0 || c.body_force[2] != 0.0;
+  const bool ibm = h->nw > 0;
+  CollideArgs ca{};
+  ca.g = h->geo;
+  ca.p = h->phys;
+  ca.du = at<float>(h, L.du);
+  ca.stamps = at<int>(h, L.stamps);
+  ca.tnx = L.tnx;
+  ca.tny = L.tny;
+  ca.nxc = L.nxc;
+  ca.nblocks = L.nblocks;
+  ca.mass_part = at<double>(h, L.mass_part);
+  ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
+  MarkerArgs ma{};
+  if (ibm) {
+    ma.g = h->geo;
+    ma.p = h->phys;
+    ma.nw = h->nw;
+    ma.m_total = h->M.m_total;
+    for (int k = 0; k < h->nw; ++k) ma.w[k] = h->wd[k];
+    ma.ref = at<double>(h, h->M.ref);
+    ma.G = at<double>(h, h->M.G);
+    ma.Minv = at<double>(h, h->M.Minv);
+    ma.X = at<double>(h, h->M.X);
+    ma.U = at<double>(h, h->M.U);
+    ma.B = at<double>(h, h->M.B);
+    ma.rhoB = at<double>(h, h->M.rhoB);
+    ma.duB = at<double>(h, h->M.duB);
+    ma.fpart = at<double>(h, h->M.fpart);
+    ma.counters = at<unsigned int>(h, h->M.counters);
+    ma.hist = at<double>(h, h->M.hist);
+    ma.u_ref = c.u_ref;
+    ma.area_ref = c.area_ref;
+    ma.du = at<float>(h, L.du);
+    ma.stamps = at<int>(h, L.stamps);
+    ma.tnx = L.tnx;
+    ma.tny = L.tny;
+    ma.flags = ca.flags;
+  }
+  for (int k = 0; k < n; ++k) {
+    const long long s = h->step;
+    const int stamp = (int)(s % 1000000000LL) + 1;
+    if (ibm) {
+      ma.t = (double)s;
+      ma.src = cur_state(h);
+      ma.hist_row = s % c.history_steps;
+      ma.stamp = stamp;
+      int rc = record_event(h, 1, true);
+      if (rc) return rc;
+      HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
+      rc = record_event(h, 1, false);
+      if (rc) return rc;
+    }
+    ca.src = cur_state(h);
+    ca.dst = next_state(h);
+    ca.stamp = stamp;
+    const bool check = c.check_interval > 0 && ((s + 1) % c.check_interval == 0);
+    int rc = record_event(h, 0, true);
+    if (rc) return rc;
+    HIP_TRY(h, launch_collide(c.storage, ibm, force, check, ca, h->stream));
+    rc = record_event(h, 0, false);
+    if (rc) return rc;
+    if (check)
+      HIP_TRY(h, launch_mass_reduce(ca.mass_part, L.nblocks, (double)L.N,
+                                    reinterpret_cast<double*>(h->ws + L.diag.off), s + 1, h->stream));
+    h->cur_is_A = !h->cur_is_A;
+    h->step = s + 1;
+    if (ibm) h->markers_valid = true;
+  }
+  return IBMLBM_OK;
+}
+
+int64_t ibmlbm_step_count(ibmlbm_t h) { return h ? h->step : -1; }
+
+int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (count < 0 || first < 0 || (count > 0 && !out)) return fail(h, IBMLBM_EINVAL, "bad range or null output");
+  if (h->nw == 0) return count == 0 ? IBMLBM_OK : fail(h, IBMLBM_ESTATE, "no foils");
+  const long long H = h->cfg.history_steps;
+  if (first + count > h->step || first < h->step - H)
+    return fail(h, IBMLBM_ERANGE, "history rows [%lld, %lld) not held (have [%lld, %lld))",
+                (long long)first, (long long)(first + count), (long long)std::max(0LL, h->step - H),
+                (long long)h->step);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  int flags = 0;
+  HIP_TRY(h, hipMemcpy(&flags, h->ws + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
+  const size_t row = (size_t)h->nw * 8;
+  const double* hist = at<double>(h, h->M.hist);
+  for (long long k = 0; k < count; ++k) {
+    const long long r = (first + k) % H;
+    HIP_TRY(h, hipMemcpy(out + k * row, hist + r * row, row * 8, hipMemcpyDeviceToHost));
+  }
+  if (flags & 2) return fail(h, IBMLBM_EDIVERGED, "a perimeter system became singular");
+  if (flags & 1) return fail(h, IBMLBM_EDIVERGED, "non-finite density seen on a check step");
+  return IBMLBM_OK;
+}
+
+int ibmlbm_fields(ibmlbm_t h, int32_t which, double* out) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (!out) return fail(h, IBMLBM_EINVAL, "null output");
+  if (!h->initialized) return fail(h, IBMLBM_ESTATE, "fields before init_fields");
+  const LatticeLayout& L = h->L;
+  const size_t N = L.N;
+  const int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
+  if (which == IBMLBM_FIELD_RHO || which == IBMLBM_FIELD_U) {
+    float* scratch = static_cast<float*>(next_state(h));
+    HIP_TRY(h, launch_moments(h->cfg.storage, h->geo, h->phys, cur_state(h), scratch, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::vector<float> host(4 * N);
+    HIP_TRY(h, hipMemcpy(host.data(), scratch, 4 * N * sizeof(float), hipMemcpyDeviceToHost));
+    if (which == IBMLBM_FIELD_RHO)
+      for (size_t i = 0; i < N; ++i) out[i] = host[i];
+    else
+      for (size_t i = 0; i < 3 * N; ++i) out[i] = host[N + i];
+    return IBMLBM_OK;
+  }
+  if (which != IBMLBM_FIELD_FDIST) return fail(h, IBMLBM_EINVAL, "unknown field %d", which);
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  std::vector<unsigned char> host((size_t)kQ * L.ps * L.es);
+  HIP_TRY(h, hipMemcpy(host.data(), cur_state(h), host.size(), hipMemcpyDeviceToHost));
+  const double w[kQ] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                        1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  for (int q = 0; q < kQ; ++q)
+    for (int z = 0; z < nz; ++z)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          const size_t cell = ((size_t)z * ny + y) * nx + x;
+          const size_t idx = (size_t)q * L.ps + ((size_t)(z * ny + y) + 1) * L.px + x;
+          float v;
+          if (L.es == 4) {
+            std::memcpy(&v, &host[idx * 4], 4);
+          } else if (h->cfg.storage == IBMLBM_FP16_DEV) {
+            _Float16 hv;
+            std::memcpy(&hv, &host[idx * 2], 2);
+            v = (float)hv;
+          } else {
+            uint16_t b16;
+            std::memcpy(&b16, &host[idx * 2], 2);
+            const uint32_t u32 = (uint32_t)b16 << 16;
+            std::memcpy(&v, &u32, 4);
+          }
+          out[(size_t)q * N + cell] = w[q] + (double)v;
+        }
+  return IBMLBM_OK;
+}
+
+int32_t ibmlbm_marker_count(ibmlbm_t h) { return h ? h->M.m_total * (h->nw > 0) : 0; }
+
+int ibmlbm_markers(ibmlbm_t h, int32_t which, double* out) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (!out) return fail(h, IBMLBM_EINVAL, "null output");
+  if (h->nw == 0) return fail(h, IBMLBM_ESTATE, "no foils");
+  const size_t m = h->M.m_total;
+  if (which == IBMLBM_MARKER_DA) {
+    for (int k = 0; k < h->nw; ++k)
+      for (int i = 0; i < h->wd[k].np * h->wd[k].ns; ++i) out[h->wd[k].moff + i] = h->wd[k].dA;
+    return IBMLBM_OK;
+  }
+  if (!h->markers_valid) return fail(h, IBMLBM_ESTATE, "no completed step with markers yet");
+  const Region* r = nullptr;
+  size_t count = 3 * m;
+  switch (which) {
+    case IBMLBM_MARKER_X: r = &h->M.X; break;
+    case IBMLBM_MARKER_U: r = &h->M.U; break;
+    case IBMLBM_MARKER_RHS: r = &h->M.B; break;
+    case IBMLBM_MARKER_DU: r = &h->M.duB; break;
+    case IBMLBM_MARKER_RHO: r = &h->M.rhoB; count = m; break;
+    default: return fail(h, IBMLBM_EINVAL, "unknown marker field %d", which);
+  }
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  HIP_TRY(h, hipMemcpy(out, h->ws + r->off, count * 8, hipMemcpyDeviceToHost));
+  return IBMLBM_OK;
+}
+
+int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass) {
+  if (!h || !step || !mass) return fail(h, IBMLBM_EINVAL, "null argument");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  double d[2];
+  int flags = 0;
+  HIP_TRY(h, hipMemcpy(d, h->ws + h->L.diag.off, 16, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&flags, h->ws + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
+  *mass = d[0];
+  *step = d[1] > 0.0 ? (int64_t)d[1] : -1;
+  if (flags & 1) return fail(h, IBMLBM_EDIVERGED, "non-finite density seen on a check step");
+  return IBMLBM_OK;
+}
+
+int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  if (enable && h->ev.empty()) {
+    const int pairs = 4096;
+    h->ev.resize(2 * pairs);
+    h->ev_kind.assign(pairs, 0);
+    for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
+  }
+  h->timing = enable != 0;
+  return IBMLBM_OK;
+}
+
+int ibmlbm_read_timing(ibmlbm_t h, double* collide_ms, int64_t* collide_launches, double* marker_ms) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+    if (h->ev_kind[k / 2] == 0) { h->acc_collide_ms += ms; h->acc_collide_n++; }
+    else h->acc_marker_ms += ms;
+  }
+  h->ev_used = 0;
+  if (collide_ms) *collide_ms = h->acc_collide_ms;
+  if (collide_launches) *collide_launches = h->acc_collide_n;
+  if (marker_ms) *marker_ms = h->acc_marker_ms;
+  h->acc_collide_ms = h->acc_marker_ms = 0.0;
+  h->acc_collide_n = 0;
+  return IBMLBM_OK;
+}
+
+int32_t ibmlbm_bytes_per_cell(ibmlbm_t h) { return h ? 2 * kQ * h->L.es : 0; }
+
+int ibmlbm_destroy(ibmlbm_t h) {
+  if (!h) return IBMLBM_OK;
+  hipError_t e = hipStreamSynchronize(h->stream);
+  for (auto& ev : h->ev) (void)hipEventDestroy(ev);
+  delete h;
+  if (e != hipSuccess) return fail(nullptr, IBMLBM_EDEVICE, "stream error at destroy: %s", hipGetErrorString(e));
+  return IBMLBM_OK;
+}
+
+const char* ibmlbm_last_error(ibmlbm_t h) { return h ? h->err.c_str() : g_err.c_str(); }
+
+int ibmlbm_lattice_params(double Re, double J, double f, double chord, double kappa, double* tau,
+                          double* u_inf, double* u_tip, double* period_steps) {
+  if (!(Re > 0.0) || !(f > 0.0) || !(chord > 0.0) || !(kappa > 0.0) || J < 0.0)
+    return fail(nullptr, IBMLBM_EINVAL, "Re, f, chord, kappa must be > 0 and J >= 0");
+  const double Phi = 2.0 * M_PI / 3.0;
+  const double ut = kappa * f;
+  const double nu = ut * chord / Re;
+  if (tau) *tau = 3.0 * nu + 0.5;
+  if (u_inf) *u_inf = J * ut;
+  if (u_tip) *u_tip = ut;
+  if (period_steps) *period_steps = 2.0 * Phi * chord / ut;
+  return IBMLBM_OK;
+}
+
+}  // extern "C"

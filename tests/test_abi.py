@@ -1,0 +1,125 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol that
+include/ibmlbm.h declares, and its host-only entry points validate input.
+No call here touches a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as WL
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ibmlbm.h")
+
+
+def _lib():
+    from paper_2102_01305_amd import _lib as L
+    return L, L.load()
+
+
+def test_every_declared_symbol_is_exported():
+    L, lib = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"IBMLBM_API[^;(]*?\b(ibmlbm_\w+)\s*\(", text))
+    assert len(declared) >= 17
+    bound = {name for name, _, _ in L.SIGNATURES}
+    assert declared == bound, declared ^ bound
+    for name in declared:
+        assert hasattr(lib, name)
+
+
+def test_struct_sizes_match_header_layout():
+    L, _ = _lib()
+    # int32 x9 (36) + pad 4 + doubles: tau, u_in[3], rho_out, body_force[3] (64)
+    # + int32 x2 (8) + doubles u_ref, area_ref (16) + int64 (8)
+    assert C.sizeof(L.Config) == 136
+    assert C.sizeof(L.Wing) == 120
+    assert L.Config.tau.offset == 40
+    assert L.Wing.alpha_shape.offset == 64
+
+
+def _cfg(bx, **kw):
+    from paper_2102_01305_amd.solver import make_config
+    return make_config(bx, **kw)
+
+
+def _plate():
+    from paper_2102_01305_amd.solver import complete_case
+    bx, wg, ph = WL.plate_case()
+    return complete_case(bx, wg, ph)
+
+
+def test_workspace_bytes_and_validation():
+    L, lib = _lib()
+    from paper_2102_01305_amd.solver import make_wings
+    bx, wg = _plate()
+    c = _cfg(bx)
+    w = make_wings(wg)
+    lat = lib.ibmlbm_workspace_bytes(C.byref(c), 0, None)
+    full = lib.ibmlbm_workspace_bytes(C.byref(c), 1, w)
+    assert 0 < lat < full
+    # two FP32 lattices of padded rows dominate: >= 2 * 19 * 4 bytes per cell
+    assert lat >= 2 * 19 * 4 * 64 * 32 * 32
+    for key, val in (("tau", 0.5), ("nx", 3)):
+        bad = dict(bx)
+        bad[key] = val
+        assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 0, None) == 0
+        assert lib.ibmlbm_last_error(None)
+    bad = dict(bx)
+    bad["bc"] = [WL.PERIODIC, WL.WALL, 1, 1, 0, 0]
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 0, None) == 0
+    bad["bc"] = [0, 0, WL.VELOCITY, 1, 0, 0]
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 0, None) == 0
+    # a plate whose support would cross the inlet
+    far = make_wings([dict(wg[0], hinge=[4.0, 15.5])])
+    assert lib.ibmlbm_workspace_bytes(C.byref(c), 1, far) == 0
+    assert b"leave the box" in lib.ibmlbm_last_error(None)
+    # non-periodic span is rejected for extruded foils
+    bad = dict(bx)
+    bad["bc"] = [2, 3, 1, 1, 1, 1]
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 1, w) == 0
+
+
+def test_fp16_workspace_is_half_the_lattice():
+    L, lib = _lib()
+    bx, wg = _plate()
+    b32 = lib.ibmlbm_workspace_bytes(C.byref(_cfg(bx, storage="fp32")), 0, None)
+    b16 = lib.ibmlbm_workspace_bytes(C.byref(_cfg(bx, storage="bf16")), 0, None)
+    assert b16 < 0.75 * b32
+
+
+def test_clap_fling_wings_accepted_and_overlap_rejected():
+    L, lib = _lib()
+    from paper_2102_01305_amd.solver import complete_case, make_wings
+    bx, wg, ph = WL.clap_fling_case()
+    bx, wg = complete_case(bx, wg, ph)
+    c = _cfg(bx)
+    assert lib.ibmlbm_workspace_bytes(C.byref(c), 2, make_wings(wg)) > 0
+    close = [dict(wg[0]), dict(wg[1], hinge=[wg[1]["hinge"][0], wg[0]["hinge"][1] - 2.0])]
+    assert lib.ibmlbm_workspace_bytes(C.byref(c), 2, make_wings(close)) == 0
+    assert b"support" in lib.ibmlbm_last_error(None)
+
+
+def test_lattice_params_agree_with_the_paper_mapping():
+    from paper_2102_01305_amd.solver import lattice_params
+    p = lattice_params(100.0, 0.01, 0.25, 20.0)
+    assert abs(p["tau"] - 0.53) < 1e-14
+    assert abs(p["u_inf"] - 5e-4) < 1e-16
+    assert abs(p["u_tip"] - 0.05) < 1e-16
+    assert abs(p["period_steps"] - 2 * (2 * math.pi / 3) * 20 / 0.05) < 1e-9
+    L, lib = _lib()
+    t = C.c_double()
+    assert lib.ibmlbm_lattice_params(-1.0, 0.0, 0.25, 20.0, 0.2, C.byref(t), None, None, None) == L.EINVAL
+
+
+def test_solver_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    from paper_2102_01305_amd.solver import Solver
+    bx, wg = _plate()
+    with pytest.raises(RuntimeError):
+        Solver(bx, wg)
