@@ -71,14 +71,41 @@ SIGNATURES = [
 _lib = None
 
 
+def _hip_runtimes():
+    """Distinct libamdhip64 files mapped into this process."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                parts = line.split()
+                if len(parts) >= 6 and "libamdhip64.so" in parts[-1]:
+                    paths.add(os.path.realpath(parts[-1]))
+    except OSError:
+        pass
+    return paths
+
+
 def load():
-    """Load libibmlbm.so (built in-tree by __graft_entry__.build())."""
+    """Load libibmlbm.so (built in-tree by __graft_entry__.build()).
+
+    torch ships its own HIP runtime with the same sonames as ROCm's
+    (libamdhip64.so.7, libhsa-runtime64.so.1).  torch is imported first so
+    that the solver binds to the runtime torch already mapped; two HIP
+    runtimes in one process would each open the GPU on their own.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2102_01305_amd.build`")
+    try:
+        import torch  # noqa: F401  (maps torch's HIP runtime before ours)
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError(f"two HIP runtimes are mapped into this process: {sorted(runtimes)}")
     for name, res, args in SIGNATURES:
         fn = getattr(lib, name)
         fn.restype = res

@@ -28,11 +28,11 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct LatticeLayout {
   int es = 4;        // bytes per stored value
   int px = 0;
-  long long ps = 0;
+  long long ps = 0;      // population stride (elements)
+  size_t total = 0;      // elements of one state buffer
   size_t N = 0;
-  int tnx = 0, tny = 0, tnz = 0;
   int nxc = 0, nblocks = 0;
-  Region fA, fB, du, stamps, mass_part, diag;
+  Region fA, fB, mass_part, diag;
   size_t end = 0;
 };
 
@@ -41,12 +41,17 @@ struct WingGeom {
   double ds = 0.0;                 // perimeter / np
   std::vector<double> ref;         // np x 2, relative to the pivot
   double rmax = 0.0;
+  int side = 0;                    // pitch of the per-layer node-box images
 };
 
+constexpr int kPwStride = 14;      // doubles per perimeter record (kernels.hip)
+
 struct MarkerLayout {
-  Region ref, G, Minv, X, U, B, rhoB, duB, fpart, counters, hist;
+  Region ref, G, Minv, pw, C, X, U, B, rhoB, duB, fpart, hist;
+  std::vector<Region> band, corr;
   size_t end = 0;
-  int m_total = 0, layers = 0;
+  int m_total = 0, layers = 0, perims = 0;
+  int minv_step = 0, pw_step = 0;
 };
 
 }  // namespace
@@ -69,6 +74,7 @@ struct ibmlbm_s {
   std::vector<WingGeom> geom;
   MarkerLayout M;
   bool markers_valid = false;       // marker outputs of a completed step exist
+  long long win_t0 = -1;            // window of precomputed perimeter factors
   // timing
   bool timing = false;
   std::vector<hipEvent_t> ev;       // pairs: start, stop
@@ -139,19 +145,15 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   L.es = c->storage == IBMLBM_FP32 ? 4 : 2;
   const int line = 128 / L.es;
   L.px = ((c->nx + 2 + line - 1) / line) * line;
-  L.ps = ((long long)c->ny * c->nz + 1) * L.px;
+  L.ps = L.px;
+  L.total = ((size_t)c->ny * c->nz + 1) * kQ * (size_t)L.px;
   L.N = (size_t)c->nx * c->ny * c->nz;
-  L.tnx = (c->nx + kTile - 1) / kTile;
-  L.tny = (c->ny + kTile - 1) / kTile;
-  L.tnz = (c->nz + kTile - 1) / kTile;
   L.nxc = (c->nx + kBlockX - 1) / kBlockX;
   L.nblocks = L.nxc * ((c->ny * c->nz + kBlockRows - 1) / kBlockRows);
   size_t o = 0;
   auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + bytes); };
-  take(L.fA, (size_t)kQ * L.ps * L.es);
-  take(L.fB, (size_t)kQ * L.ps * L.es);
-  take(L.du, 3 * L.N * sizeof(float));
-  take(L.stamps, (size_t)L.tnx * L.tny * L.tnz * sizeof(int));
+  take(L.fA, L.total * L.es);
+  take(L.fB, L.total * L.es);
   take(L.mass_part, (size_t)L.nblocks * sizeof(double));
   take(L.diag, 64);
   L.end = o;
@@ -297,6 +299,30 @@ void perimeter_xy(const ibmlbm_wing& w, const WingGeom& g, double t, std::vector
   }
 }
 
+// Node box of one foil at time t: every support node floor(X)-1 .. floor(X)+2
+// of its markers, with one spare cell on each side against rounding
+// differences between host and device trigonometry; clipped to the box.
+void node_box(const ibmlbm_wing& w, const WingGeom& g, double t, const ibmlbm_config& c,
+              WingDev& d) {
+  std::vector<double> xy;
+  perimeter_xy(w, g, t, xy);
+  double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+  for (int p = 0; p < g.np; ++p) {
+    x0 = std::min(x0, xy[2 * p]);
+    x1 = std::max(x1, xy[2 * p]);
+    y0 = std::min(y0, xy[2 * p + 1]);
+    y1 = std::max(y1, xy[2 * p + 1]);
+  }
+  const int bx0 = std::max(0, (int)std::floor(x0) - 2);
+  const int bx1 = std::min(c.nx - 1, (int)std::floor(x1) + 3);
+  const int by0 = std::max(0, (int)std::floor(y0) - 2);
+  const int by1 = std::min(c.ny - 1, (int)std::floor(y1) + 3);
+  d.x0 = bx0;
+  d.y0 = by0;
+  d.bw = std::min(bx1 - bx0 + 1, g.side);
+  d.bh = std::min(by1 - by0 + 1, g.side);
+}
+
 // Smallest Cholesky pivot of the perimeter block relative to its largest
 // diagonal entry; <= 0 means not positive definite.
 double perimeter_conditioning(const std::vector<double>& xy, int n, const ibmlbm_config& c) {
@@ -371,20 +397,20 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
     if (x.pivot_frac < 0.0 || x.pivot_frac > 1.0) { why = "pivot_frac must be in [0, 1]"; return IBMLBM_EINVAL; }
     int rc = wing_geometry(x, geo[k], why);
     if (rc) return rc;
-    // supports on non-periodic axes: every node floor(X)-1 .. floor(X)+2 inside
+    // every support node floor(X)-1 .. floor(X)+2 stays inside the box in x
+    // and y (also on periodic axes: the node boxes of a foil do not wrap)
     const double reach = geo[k].rmax + std::fabs(x.trans_amp);
-    if (c.bc[0] != IBMLBM_BC_PERIODIC &&
-        (x.hinge[0] - reach < 1.0 || x.hinge[0] + reach >= c.nx - 2.0)) {
+    if (x.hinge[0] - reach < 1.0 || x.hinge[0] + reach >= c.nx - 2.0) {
       snprintf(b, sizeof b, "foil %d: marker supports may leave the box along x", k);
       why = b;
       return IBMLBM_EINVAL;
     }
-    if (c.bc[2] != IBMLBM_BC_PERIODIC &&
-        (x.hinge[1] - reach < 1.0 || x.hinge[1] + reach >= c.ny - 2.0)) {
+    if (x.hinge[1] - reach < 1.0 || x.hinge[1] + reach >= c.ny - 2.0) {
       snprintf(b, sizeof b, "foil %d: marker supports may leave the box along y", k);
       why = b;
       return IBMLBM_EINVAL;
     }
+    geo[k].side = 2 * (int)std::ceil(reach) + 8;
   }
   // sampled over one period of the slowest foil: separation of supports and
   // conditioning of every perimeter block
@@ -429,20 +455,31 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
     nMinv += (size_t)geo[k].np * geo[k].np;
     M.m_total += geo[k].np * c.nz;
     M.layers += c.nz;
+    M.perims += geo[k].np;
   }
   size_t o = align256(start);
   auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + std::max<size_t>(bytes, 8)); };
   const size_t m = M.m_total;
   take(M.ref, nref * 8);
   take(M.G, nG * 8);
-  take(M.Minv, nMinv * 8);
+  take(M.Minv, (size_t)kFactorWindow * nMinv * 8);
+  take(M.pw, (size_t)kFactorWindow * M.perims * kPwStride * 8);
+  M.minv_step = (int)nMinv;
+  M.pw_step = M.perims * kPwStride;
+  take(M.C, 3 * m * 8);
   take(M.X, 3 * m * 8);
   take(M.U, 3 * m * 8);
   take(M.B, 3 * m * 8);
   take(M.rhoB, m * 8);
   take(M.duB, 3 * m * 8);
-  take(M.fpart, 4 * (size_t)M.layers * 8);
-  take(M.counters, (size_t)std::max(nw, 1) * 4);
+  take(M.fpart, 4 * (size_t)M.perims * 8);
+  M.band.resize(nw);
+  M.corr.resize(nw);
+  for (int k = 0; k < nw; ++k) {
+    const size_t img = (size_t)geo[k].side * geo[k].side * c.nz * 16;
+    take(M.band[k], img);
+    take(M.corr[k], img);
+  }
   take(M.hist, (size_t)c.history_steps * std::max(nw, 1) * 8 * 8);
   M.end = o;
   return M;
@@ -522,9 +559,7 @@ int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, v
   h->geo.bclo = cfg->bc[0];
   h->geo.bchi = cfg->bc[1];
   fill_phys(h);
-  hipError_t e = hipMemsetAsync(h->ws + L.du.off, 0, L.du.bytes, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.stamps.off, 0, L.stamps.bytes, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
+  hipError_t e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     int r = fail(nullptr, IBMLBM_EDEVICE, "workspace clear failed: %s", hipGetErrorString(e));
@@ -547,7 +582,7 @@ int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const dou
     const double w[kQ] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
                           1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
-    std::vector<unsigned char> host((size_t)kQ * L.ps * L.es, 0);
+    std::vector<unsigned char> host(L.total * L.es, 0);
     const int nx = h->cfg.nx, ny = h->cfg.ny, nz = h->cfg.nz;
     for (int q = 0; q < kQ; ++q)
       for (int z = 0; z < nz; ++z)
@@ -555,7 +590,7 @@ int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const dou
           for (int x = 0; x < nx; ++x) {
             const size_t cell = ((size_t)z * ny + y) * nx + x;
             const float v = (float)(fdist[(size_t)q * N + cell] - w[q]);
-            const size_t idx = (size_t)q * L.ps + ((size_t)(z * ny + y) + 1) * L.px + x;
+            const size_t idx = (((size_t)(z * ny + y) + 1) * kQ + q) * L.px + x;
             if (L.es == 4) {
               std::memcpy(&host[idx * 4], &v, 4);
             } else if (h->cfg.storage == IBMLBM_FP16_DEV) {
@@ -584,12 +619,11 @@ int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const dou
     HIP_TRY(h, hipStreamSynchronize(h->stream));
   }
   HIP_TRY(h, launch_ghost(h->cfg.storage, h->geo, h->phys, dst, h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->ws + L.stamps.off, 0, L.stamps.bytes, h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->ws + L.du.off, 0, L.du.bytes, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->step = step0;
   h->initialized = true;
   h->markers_valid = false;
+  h->win_t0 = -1;
   return IBMLBM_OK;
 }
 
@@ -607,9 +641,10 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
   h->geom = geo;
   h->M = M;
   h->markers_valid = false;
+  h->win_t0 = -1;
   if (n_wings == 0) return IBMLBM_OK;
   std::vector<double> ref, G;
-  int moff = 0, roff = 0, goff = 0, moff2 = 0, loff = 0;
+  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, poff = 0;
   for (int k = 0; k < n_wings; ++k) {
     const ibmlbm_wing& w = wings[k];
     h->wings[k] = w;
@@ -620,7 +655,12 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     d.ref_off = roff;
     d.g_off = goff;
     d.minv_off = moff2;
-    d.layer_off = loff;
+    d.pw_off = pwoff;
+    d.c_off = 3 * moff;
+    d.side = geo[k].side;
+    d.band = at<float4>(h, M.band[k]);
+    d.corr = at<float4>(h, M.corr[k]);
+    d.fpart = at<double>(h, M.fpart) + 4 * poff;
     d.shape = w.alpha_shape;
     d.hinge0[0] = w.hinge[0];
     d.hinge0[1] = w.hinge[1];
@@ -642,11 +682,11 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     roff += 2 * d.np;
     goff += d.ns;
     moff2 += d.np * d.np;
-    loff += d.ns;
+    pwoff += kPwStride * d.np;
+    poff += d.np;
   }
   HIP_TRY(h, hipMemcpyAsync(h->ws + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->ws + M.G.off, G.data(), G.size() * 8, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->ws + M.counters.off, 0, M.counters.bytes, h->stream));
   HIP_TRY(h, hipMemsetAsync(h->ws + M.hist.off, 0, M.hist.bytes, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return IBMLBM_OK;
@@ -661,17 +701,19 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
   const bool force = c.body_force[0] != 0.0 || c.body_force[1] != 0.0 || c.body_force[2] != 0.0;
   const bool ibm = h->nw > 0;
   CollideArgs ca{};
+  MarkerArgs ma{};
   ca.g = h->geo;
   ca.p = h->phys;
-  ca.du = at<float>(h, L.du);
-  ca.stamps = at<int>(h, L.stamps);
-  ca.tnx = L.tnx;
-  ca.tny = L.tny;
+  ca.nw = h->nw;
   ca.nxc = L.nxc;
+  {
+    const float e = (float)delta_h(1.5), d = (float)delta_h(0.5);
+    ca.wz[0] = e; ca.wz[1] = d; ca.wz[2] = d; ca.wz[3] = e;
+    ma.wz[0] = delta_h(1.5); ma.wz[1] = delta_h(0.5); ma.wz[2] = delta_h(0.5); ma.wz[3] = delta_h(1.5);
+  }
   ca.nblocks = L.nblocks;
   ca.mass_part = at<double>(h, L.mass_part);
   ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
-  MarkerArgs ma{};
   if (ibm) {
     ma.g = h->geo;
     ma.p = h->phys;
@@ -686,25 +728,42 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
     ma.B = at<double>(h, h->M.B);
     ma.rhoB = at<double>(h, h->M.rhoB);
     ma.duB = at<double>(h, h->M.duB);
-    ma.fpart = at<double>(h, h->M.fpart);
-    ma.counters = at<unsigned int>(h, h->M.counters);
+    ma.pw = at<double>(h, h->M.pw);
+    ma.C = at<double>(h, h->M.C);
+    ma.pw_step = h->M.pw_step;
+    ma.minv_step = h->M.minv_step;
     ma.hist = at<double>(h, h->M.hist);
     ma.u_ref = c.u_ref;
     ma.area_ref = c.area_ref;
-    ma.du = at<float>(h, L.du);
-    ma.stamps = at<int>(h, L.stamps);
-    ma.tnx = L.tnx;
-    ma.tny = L.tny;
     ma.flags = ca.flags;
   }
   for (int k = 0; k < n; ++k) {
     const long long s = h->step;
-    const int stamp = (int)(s % 1000000000LL) + 1;
     if (ibm) {
+      if (h->win_t0 < 0 || s < h->win_t0 || s >= h->win_t0 + kFactorWindow) {
+        h->win_t0 = s;
+        ma.win_t0 = s;
+        HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
+      }
+      ma.win_t0 = h->win_t0;
+      ma.slot = (int)(s - h->win_t0);
       ma.t = (double)s;
       ma.src = cur_state(h);
       ma.hist_row = s % c.history_steps;
-      ma.stamp = stamp;
+      long long cells = 0;
+      for (int w = 0; w < h->nw; ++w) {
+        node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
+        FoilBox& b = ca.box[w];
+        b.x0 = ma.w[w].x0; b.y0 = ma.w[w].y0; b.w = ma.w[w].bw; b.h = ma.w[w].bh;
+        b.side = ma.w[w].side;
+        b.band = ma.w[w].band;
+        b.corr = ma.w[w].corr;
+        cells += (long long)b.w * b.h * c.nz;
+      }
+      ma.band_cells = (int)cells;
+      long long box_rows = 0;
+      for (int w = 0; w < h->nw; ++w) box_rows += (long long)ma.w[w].bh * c.nz;
+      ma.band_blocks = (int)((box_rows + 3) / 4);
       int rc = record_event(h, 1, true);
       if (rc) return rc;
       HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
@@ -713,7 +772,6 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
     }
     ca.src = cur_state(h);
     ca.dst = next_state(h);
-    ca.stamp = stamp;
     const bool check = c.check_interval > 0 && ((s + 1) % c.check_interval == 0);
     int rc = record_event(h, 0, true);
     if (rc) return rc;
@@ -776,7 +834,7 @@ int ibmlbm_fields(ibmlbm_t h, int32_t which, double* out) {
   }
   if (which != IBMLBM_FIELD_FDIST) return fail(h, IBMLBM_EINVAL, "unknown field %d", which);
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  std::vector<unsigned char> host((size_t)kQ * L.ps * L.es);
+  std::vector<unsigned char> host(L.total * L.es);
   HIP_TRY(h, hipMemcpy(host.data(), cur_state(h), host.size(), hipMemcpyDeviceToHost));
   const double w[kQ] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
                         1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
@@ -786,7 +844,7 @@ int ibmlbm_fields(ibmlbm_t h, int32_t which, double* out) {
       for (int y = 0; y < ny; ++y)
         for (int x = 0; x < nx; ++x) {
           const size_t cell = ((size_t)z * ny + y) * nx + x;
-          const size_t idx = (size_t)q * L.ps + ((size_t)(z * ny + y) + 1) * L.px + x;
+          const size_t idx = (((size_t)(z * ny + y) + 1) * kQ + q) * L.px + x;
           float v;
           if (L.es == 4) {
             std::memcpy(&v, &host[idx * 4], 4);
@@ -852,7 +910,8 @@ int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
     const int pairs = 4096;
     h->ev.resize(2 * pairs);
     h->ev_kind.assign(pairs, 0);
-    for (auto& e : h->ev) HIP_TRY(h, hipEventCreate(&e));
+    // no system-scope fence: the events only time kernels on this device
+    for (auto& e : h->ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
   h->timing = enable != 0;
   return IBMLBM_OK;

@@ -12,20 +12,21 @@ namespace ibmk {
 constexpr int kQ = 19;
 constexpr int kMaxWings = 8;
 constexpr int kMaxPerim = 128;     // perimeter markers per foil (LDS of the inversion)
-constexpr int kTile = 8;           // tile edge of the marker-band flags
 constexpr int kBlockX = 64;        // collide block: 64 cells along x ...
-constexpr int kBlockRows = 4;      // ... times 4 rows
+constexpr int kBlockRows = 4;      // ... times 4 rows, one row per wave
+constexpr int kFactorWindow = 64;  // steps whose perimeter factors are made at once
 
 enum Bc { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
-// Padded distribution layout: population q, row r = z*ny + y, cell x lives at
-// element q*ps + (r+1)*px + x.  Element (r+1)*px - 1 is the x = -1 ghost of
-// row r and (r+1)*px + nx the x = nx ghost; px >= nx + 2 and px*elem is a
-// multiple of 128 bytes so every row starts on a cache line.
+// Padded distribution layout, row-major slabs: population q of row
+// r = z*ny + y, cell x, lives at element ((r+1)*19 + q)*px + x.  The element
+// before x = 0 is the x = -1 ghost of that (row, population) and element nx
+// the x = nx ghost; px >= nx + 2 and px*elem is a multiple of 128 bytes so
+// every population row starts on a cache line.  The first slab is padding.
 struct Geo {
   int nx, ny, nz, px;
-  long long ps;
+  long long ps;        // population stride within a slab (= px)
   int yper, zper;      // periodic y / z
   int bclo, bchi;      // kinds of the -x / +x faces
 };
@@ -38,15 +39,25 @@ struct Phys {
   float rho_out;       // density of PRESSURE faces
 };
 
+// Per foil and step: the xy box of lattice nodes that its markers' kernel
+// supports can reach (identical for every span layer of an extruded foil).
+// Band moments and the spread correction are stored over this box, with a
+// fixed pitch `side` (the largest box the motion can produce).
+struct FoilBox {
+  int x0, y0, w, h;    // box origin and size for this step
+  int side;            // pitch of the per-layer images
+  const float4* band;  // [nz][side][side] rho, u*x, u*y, u*z
+  const float4* corr;  // [nz][side][side] du_x, du_y, du_z, 0 (spread result)
+};
+
 struct CollideArgs {
   Geo g;
   Phys p;
   const void* src;
   void* dst;
-  float* du;                 // 3 planes of N floats (marker-band velocity correction)
-  const int* stamps;         // per-tile stamp of the last spread
-  int stamp;                 // stamp value meaning "spread this step"
-  int tnx, tny;              // tiles along x and y
+  int nw;                    // foils whose correction the kernel applies
+  FoilBox box[kMaxWings];
+  float wz[4];               // span weights delta(1.5), delta(0.5), delta(0.5), delta(1.5)
   int nxc;                   // 64-wide chunks along x
   int nblocks;
   double* mass_part;         // per-block partial sums (check steps)
@@ -58,10 +69,15 @@ struct WingDev {
   int ref_off;               // offset of this foil's (np x 2) reference coordinates
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
-  int layer_off;             // offset of this foil's span layers in the force partials
+  int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
+  int c_off;                 // offset of this foil's intermediate C (np x 3 x ns)
   int shape;
   double hinge0[2], theta0, sense, mean, amp, period, phase, tamp, tang;
   double dA, chord;
+  int x0, y0, bw, bh, side;  // this step's node box (see FoilBox)
+  float4* band;              // band moments over the box
+  float4* corr;              // spread correction over the box
+  double* fpart;             // per perimeter marker: Fx, Fy, Fz, Mz of its span column
 };
 
 struct MarkerArgs {
@@ -69,26 +85,28 @@ struct MarkerArgs {
   Phys p;
   int nw;
   int m_total;
+  int band_cells;            // sum over foils of bw*bh*nz
+  int band_blocks;           // blocks of 4 box rows
   WingDev w[kMaxWings];
+  double wz[4];              // span weights of a node at offsets -1.5, -0.5, 0.5, 1.5
   double t;
   const void* src;           // current state (post-collision of the previous step)
   const double* ref;
   const double* G;
-  double* Minv;
+  double* Minv;              // [window slot][sum np^2] perimeter inverses
+  double* pw;                // [window slot][sum np x 14] perimeter records
+  long long win_t0;          // first step of the precomputed window
+  int slot;                  // this step's slot in the window
+  int pw_step, minv_step;    // doubles per slot
+  double* C;
   double* X;                 // 3 per marker
   double* U;                 // 3 per marker
   double* B;                 // 3 per marker
   double* rhoB;              // 1 per marker
   double* duB;               // 3 per marker
-  double* fpart;             // per (wing, span layer): Fx, Fy, Fz, Mz
-  unsigned int* counters;    // per wing: finished span blocks this step
   double* hist;              // [H][nw][8]
   long long hist_row;        // row of this step in the ring
   double u_ref, area_ref;
-  float* du;                 // lattice velocity-correction planes
-  int* stamps;
-  int stamp;
-  int tnx, tny;
   int* flags;                // bit 1: singular perimeter system
 };
 
@@ -102,6 +120,7 @@ hipError_t launch_moments(int storage, const Geo& g, const Phys& p, const void* 
                           float* out, hipStream_t s);
 hipError_t launch_mass_reduce(const double* part, int n, double ncells, double* out,
                               long long step, hipStream_t s);
+hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s);
 hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s);
 
 }  // namespace ibmk

@@ -4,14 +4,15 @@
 //            forcing and BGK relaxation over every cell (Eqs. 1-11, 16, 26);
 //            also writes the x-face ghost layer of the next state.
 //  ghost     the same ghost rule for a freshly initialised state.
-//  factor    perimeter block of the no-slip matrix and its inverse (Eq. 18).
-//  interp    marker kinematics (Eqs. 20-23) and delta interpolation of rho and
-//            u* to the markers, right-hand side B (Eqs. 14, 17, 19).
-//  solve     minimum-norm solution of A X = B (Eq. 19) for one span layer of
-//            one foil, then the force and moment on it (Eq. 26); the last
-//            layer block of a foil writes the coefficients to the history.
-//  spread    du(x) = sum_l du_B D dA (Eq. 15) with float atomics, and marks
-//            the 8^3 tiles the collide kernel must correct.
+//  factor    marker kinematics (Eqs. 20-23), the perimeter block of the
+//            no-slip matrix and its inverse (Eq. 18), for a window of steps.
+//  band      rho, u* over the node box of each foil (Eqs. 2, 11).
+//  interp    delta interpolation of rho and u* to the markers (Eqs. 14, 17),
+//            B = U_B - I u* (Eq. 19), then the perimeter solve per layer.
+//  span      the span part of the minimum-norm solve (Eq. 19), du_B, and the
+//            force and moment of each span column (Eq. 26).
+//  forces    per foil: fixed-order sum of the columns, coefficients, history.
+//  spread    sum_l du_B D dA over each layer of each foil's box (Eq. 15).
 //
 // Distributions are stored as deviations from the lattice weights,
 // f~_i = f_i - w_i, so FP32 (and 16-bit) storage keeps the small velocity
@@ -47,57 +48,74 @@ __host__ __device__ constexpr double wqd(int i) {
 }
 
 // ---------------------------------------------------------------- storage --
+// st() is a plain store; stn() a streaming (non-temporal) store for data
+// that the current kernel will not read again.
 struct StF32 {
   using T = float;
   __device__ static float ld(const T* p) { return *p; }
   __device__ static void st(T* p, float v) { *p = v; }
+  __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 struct StF16 {
   using T = __half;
   __device__ static float ld(const T* p) { return __half2float(*p); }
   __device__ static void st(T* p, float v) { *p = __float2half_rn(v); }
+  __device__ static void stn(T* p, float v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), reinterpret_cast<unsigned short*>(p));
+  }
 };
 struct StBF16 {
   using T = unsigned short;
   __device__ static float ld(const T* p) { return __uint_as_float(((unsigned)*p) << 16); }
-  __device__ static void st(T* p, float v) {
+  __device__ static unsigned short enc(float v) {
     unsigned u = __float_as_uint(v);
     u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
-    *p = (unsigned short)(u >> 16);
+    return (unsigned short)(u >> 16);
   }
+  __device__ static void st(T* p, float v) { *p = enc(v); }
+  __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
 };
 
+// Row-major slabs: the 19 populations of one lattice row are adjacent, so a
+// wave's 19 loads and 19 stores stay within a few DRAM pages.
 __device__ __forceinline__ long long rowbase(const Geo& g, int y, int z) {
-  return (long long)(z * g.ny + y + 1) * g.px;
+  return (long long)(z * g.ny + y + 1) * (kQ * g.px);
 }
 
 // Pre-collision distributions of cell (x, y, z): pull f~_i from x - c_i of
 // the post-collision state S.  y/z: periodic wrap or half-way bounce-back
 // (f_i <- S_opp(i) of the cell itself).  x: through the ghost layer, which
 // holds the periodic image, the bounce-back value or the inlet/outlet
-// equilibrium.
+// equilibrium.  All 19 source rows are chosen first, without branches, so
+// the loads issue back to back; when y and z are wave-uniform the row
+// pointers stay in scalar registers.
 template <class St>
 __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, const Geo& g,
                                        int x, int y, int z, float f[kQ]) {
-  const long long own = rowbase(g, y, z) + x;
+  using T = typename St::T;
+  const T* src[kQ];
+  const T* own = S + rowbase(g, y, z);
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
     const int cy = cyq(i), cz = czq(i), cx = cxq(i);
     int yy = y - cy, zz = z - cz;
     bool wall = false;
     if (cy != 0) {
-      if (yy < 0) { if (g.yper) yy += g.ny; else wall = true; }
-      else if (yy >= g.ny) { if (g.yper) yy -= g.ny; else wall = true; }
+      const bool out = yy < 0 || yy >= g.ny;
+      wall = wall || (out && !g.yper);
+      yy = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
     }
     if (cz != 0) {
-      if (zz < 0) { if (g.zper) zz += g.nz; else wall = true; }
-      else if (zz >= g.nz) { if (g.zper) zz -= g.nz; else wall = true; }
+      const bool out = zz < 0 || zz >= g.nz;
+      wall = wall || (out && !g.zper);
+      zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
     }
-    if (wall)
-      f[i] = St::ld(S + (long long)oppq(i) * g.ps + own);
-    else
-      f[i] = St::ld(S + (long long)i * g.ps + rowbase(g, yy, zz) + x - cx);
+    const T* pn = S + (long long)i * g.ps + rowbase(g, yy, zz) - cx;
+    const T* pb = own + (long long)oppq(i) * g.ps;
+    src[i] = wall ? pb : pn;
   }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) f[i] = St::ld(src[i] + x);
 }
 
 // Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
@@ -170,15 +188,6 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
   }
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
-// that each XCD streams one contiguous slab and the x-neighbour cache lines
-// of a row stay in one L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-  const int xcd = b & 7, local = b >> 3;
-  const int per = nb >> 3, rem = nb & 7;
-  return xcd * per + (xcd < rem ? xcd : rem) + local;
-}
-
 // ---------------------------------------------------------------- collide --
 template <class St, bool IBM, bool FORCE, bool CHECK>
 __global__ void __launch_bounds__(kBlockX * kBlockRows)
@@ -187,17 +196,18 @@ k_collide(CollideArgs a) {
   const Geo& g = a.g;
   const T* __restrict__ S = static_cast<const T*>(a.src);
   T* __restrict__ D = static_cast<T*>(a.dst);
-  const int lb = xcd_remap(blockIdx.x, a.nblocks);
+  const int lb = blockIdx.x;
   const int xc = lb % a.nxc;
   const int rg = lb / a.nxc;
   const int x = xc * kBlockX + threadIdx.x;
-  const int row = rg * kBlockRows + threadIdx.y;
+  // one row per wave: make the row index wave-uniform for the compiler
+  const int row = __builtin_amdgcn_readfirstlane(rg * kBlockRows + (int)threadIdx.y);
   const bool active = x < g.nx && row < g.ny * g.nz;
   double dm = 0.0;
   bool bad = false;
   if (active) {
-    const int z = row / g.ny;
-    const int y = row - z * g.ny;
+    const int z = __builtin_amdgcn_readfirstlane(row / g.ny);
+    const int y = __builtin_amdgcn_readfirstlane(row - z * g.ny);
     float f[kQ];
     pull19<St>(S, g, x, y, z, f);
     float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
@@ -218,14 +228,26 @@ k_collide(CollideArgs a) {
     float ux = jx * inv, uy = jy * inv, uz = jz * inv;
     bool forced = FORCE;
     if (IBM) {
-      const int tile = ((z >> 3) * a.tny + (y >> 3)) * a.tnx + (x >> 3);
-      if (a.stamps[tile] == a.stamp) {
-        const size_t N = (size_t)g.nx * g.ny * g.nz;
-        const size_t cell = ((size_t)z * g.ny + y) * g.nx + x;
-        const float dux = a.du[cell], duy = a.du[N + cell], duz = a.du[2 * N + cell];
-        a.du[cell] = 0.f;
-        a.du[N + cell] = 0.f;
-        a.du[2 * N + cell] = 0.f;
+      // du(x) = sum over foils and the 4 span layers within reach of the
+      // layer images written by the spread kernel (Eq. 15)
+      float dux = 0.f, duy = 0.f, duz = 0.f;
+      bool hit = false;
+      for (int w = 0; w < a.nw; ++w) {
+        const FoilBox& b = a.box[w];
+        const int lx = x - b.x0, ly = y - b.y0;
+        if (ly < 0 || ly >= b.h || lx < 0 || lx >= b.w) continue;
+        hit = true;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          int s = z - 2 + k;
+          s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
+          const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
+          dux += a.wz[k] * v.x;
+          duy += a.wz[k] * v.y;
+          duz += a.wz[k] * v.z;
+        }
+      }
+      if (hit) {
         ux += dux; uy += duy; uz += duz;                 // Eq. 16
         Fx += 2.0f * rho * dux;                          // Eq. 11 / Eq. 26
         Fy += 2.0f * rho * duy;
@@ -248,9 +270,9 @@ k_collide(CollideArgs a) {
         o[i] += k * wq(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);   // Eq. 8
       }
     }
-    const long long own = rowbase(g, y, z) + x;
+    T* own = D + rowbase(g, y, z);
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) St::st(D + (long long)i * g.ps + own, o[i]);
+    for (int i = 0; i < kQ; ++i) St::stn(own + (long long)i * g.ps + x, o[i]);
     if (x == 0 || x == g.nx - 1) write_ghosts<St>(D, g, a.p, x, y, z, o);
     if (CHECK) {
       dm = (double)drho;
@@ -428,6 +450,17 @@ hipError_t launch_mass_reduce(const double* part, int n, double ncells, double* 
 }
 
 // ---------------------------------------------------------------- markers --
+//
+// An extruded foil has the same perimeter section on every span layer
+// z = s + 1/2, so D = delta_x delta_y delta_z splits into a perimeter part
+// (per step) and a span part whose node weights are the constants
+// delta(1.5), delta(0.5), delta(0.5), delta(1.5).  The no-slip matrix is then
+// M_xy (x) M_z with M = I I^T, and its minimum-norm solution is
+// (M_xy^-1 (x) M_z^+) B (Eqs. 18-19).
+//
+// Per-step perimeter record (stride kPw doubles): X, Y, rx, ry, wx[4], wy[4],
+// bx, by; rx, ry = R(theta) ref, bx/by = floor(X) - 1 (first support node).
+constexpr int kPw = 14;
 
 // Eq. 14: (1 + cos(pi |r| / 2)) / 4 for |r| <= 2, else 0.
 __device__ __forceinline__ double delta_k(double r) {
@@ -471,77 +504,61 @@ __device__ void wing_pose(const WingDev& w, double t, double& th, double& thd, d
   }
 }
 
-__device__ __forceinline__ int find_wing(const MarkerArgs& a, int m) {
-  int w = 0;
-  for (int k = 1; k < a.nw; ++k)
-    if (m >= a.w[k].moff) w = k;
-  return w;
-}
-
-// Position of marker (p, s) of foil w.
-__device__ __forceinline__ void marker_pos(const MarkerArgs& a, const WingDev& w, int p, int s,
-                                           double c, double sn, double hx, double hy,
-                                           double& X, double& Y, double& Z, double& rx, double& ry) {
-  const double px = a.ref[w.ref_off + 2 * p], py = a.ref[w.ref_off + 2 * p + 1];
-  rx = c * px - sn * py;
-  ry = sn * px + c * py;
-  X = hx + rx;
-  Y = hy + ry;
-  Z = s + 0.5;
-}
-
-// 1D weights of a point: nodes b .. b+3 with b = floor(X) - 1.
-__device__ __forceinline__ int weights4(double X, double w[4]) {
-  const double fb = floor(X) - 1.0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) w[k] = delta_k(fb + k - X);
-  return (int)fb;
-}
-
-__device__ __forceinline__ int wrapi(int i, int n, int per) {
-  if (!per) return i;
-  i %= n;
-  return i < 0 ? i + n : i;
-}
-
-// a(p, q) = sum_j delta(j - p) delta(j - q): 1D factor of Eq. 18.
-__device__ __forceinline__ double a1(const double wp[4], int bp, double q, int n, int per) {
+// a(p, q) = sum_j delta(j - X_p) delta(j - X_q) from the two 4-node weight
+// sets (1D factor of Eq. 18).
+__device__ __forceinline__ double a1(const double* wp, int bp, const double* wq, int bq) {
+  const int d = bq - bp;
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    double r = (double)(bp + k) - q;
-    if (per) r -= n * rint(r / n);
-    s += wp[k] * delta_k(r);
+    const int kk = k - d;
+    if (kk >= 0 && kk < 4) s += wp[k] * wq[kk];
   }
   return s;
 }
 
-// Perimeter block of M = I I^T (Eq. 18 with dA factored out):
-// M_xy[p][q] = a(x_p, x_q) a(y_p, y_q), inverted in place by Gauss-Jordan
-// (symmetric positive definite, no pivoting), in FP64 in LDS.
+// Perimeter positions and weights of foil `wi` at time t, the block
+// M_xy[p][q] = a(X_p, X_q) a(Y_p, Y_q) and its inverse by in-place
+// Gauss-Jordan (symmetric positive definite: no pivoting), FP64 in LDS.
+// These depend on the prescribed kinematics only, so they are computed for a
+// window of future steps at once, one block per (step, foil).
 __global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
   extern __shared__ double lds[];
-  const WingDev& w = a.w[blockIdx.x];
+  const int slot = blockIdx.x / a.nw, wi = blockIdx.x - slot * a.nw;
+  const WingDev& w = a.w[wi];
   const int n = w.np;
-  double* M = lds;                       // n*n
-  double* px = lds + n * n;              // n x-positions
-  double* py = px + n;
+  double* M = lds;              // n * n
+  double* P = lds + n * n;      // n * kPw
+  double* colk = P + n * kPw;   // n
   double th, thd, hx, hy, vx, vy;
-  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  wing_pose(w, (double)(a.win_t0 + slot), th, thd, hx, hy, vx, vy);
   const double c = cos(th), sn = sin(th);
+  double* Pg = a.pw + (size_t)slot * a.pw_step + w.pw_off;
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    double X, Y, Z, rx, ry;
-    marker_pos(a, w, p, 0, c, sn, hx, hy, X, Y, Z, rx, ry);
-    px[p] = X;
-    py[p] = Y;
+    const double px = a.ref[w.ref_off + 2 * p], py = a.ref[w.ref_off + 2 * p + 1];
+    const double rx = c * px - sn * py, ry = sn * px + c * py;
+    const double X = hx + rx, Y = hy + ry;
+    double* r = P + p * kPw;
+    r[0] = X;
+    r[1] = Y;
+    r[2] = rx;
+    r[3] = ry;
+    const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r[4 + k] = delta_k(fx + k - X);
+      r[8 + k] = delta_k(fy + k - Y);
+    }
+    r[12] = fx;
+    r[13] = fy;
   }
   __syncthreads();
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) Pg[e] = P[e];
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int p = e / n, q = e - p * n;
-    double wx[4], wy[4];
-    const int bx = weights4(px[p], wx), by = weights4(py[p], wy);
-    M[e] = a1(wx, bx, px[q], a.g.nx, a.g.bclo == BC_PERIODIC) *
-           a1(wy, by, py[q], a.g.ny, a.g.yper);
+    const double* rp = P + p * kPw;
+    const double* rq = P + q * kPw;
+    M[e] = a1(rp + 4, (int)rp[12], rq + 4, (int)rq[12]) * a1(rp + 8, (int)rp[13], rq + 8, (int)rq[13]);
   }
   __syncthreads();
   __shared__ int singular;
@@ -554,9 +571,6 @@ __global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
       break;
     }
     const double ip = 1.0 / piv;
-    __syncthreads();
-    // column k of the other rows (saved before the row update overwrites it)
-    double* colk = py;  // reuse: positions no longer needed
     for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = M[i * n + k];
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) M[k * n + j] = (j == k ? 1.0 : M[k * n + j]) * ip;
@@ -571,114 +585,188 @@ __global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
   }
   __syncthreads();
   if (singular && threadIdx.x == 0) atomicOr(a.flags, 2);
-  double* out = a.Minv + w.minv_off;
+  double* out = a.Minv + (size_t)slot * a.minv_step + w.minv_off;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) out[e] = M[e];
 }
 
-// One wave per marker, one lane per node of its 4x4x4 support.
+// rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
+// pre-collision state at every node of every foil's box, on every layer.
+// One wave per box row (y, z), lanes along x, so rows are wave-uniform.
 template <class St>
-__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
+__global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
   using T = typename St::T;
+  int R = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= a.m_total) return;
-  const int wi = find_wing(a, m);
+  int wi = 0;
+  while (wi < a.nw) {
+    const int rows = a.w[wi].bh * a.g.nz;
+    if (R < rows) break;
+    R -= rows;
+    ++wi;
+  }
+  if (wi >= a.nw) return;
   const WingDev& w = a.w[wi];
-  const int local = m - w.moff;
-  const int p = local / w.ns, s = local - p * w.ns;
-  double th, thd, hx, hy, vx, vy;
-  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
-  const double c = cos(th), sn = sin(th);
-  double X, Y, Z, rx, ry;
-  marker_pos(a, w, p, s, c, sn, hx, hy, X, Y, Z, rx, ry);
-  double wx[4], wy[4], wz[4];
-  const int bx = weights4(X, wx), by = weights4(Y, wy), bz = weights4(Z, wz);
-  const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-  const Geo& g = a.g;
-  const int nx = wrapi(bx + ox, g.nx, g.bclo == BC_PERIODIC);
-  const int ny = wrapi(by + oy, g.ny, g.yper);
-  const int nz = wrapi(bz + oz, g.nz, g.zper);
-  const double Dw = wx[ox] * wy[oy] * wz[oz];
-  float f[kQ];
-  pull19<St>(static_cast<const T*>(a.src), g, nx, ny, nz, f);
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+  const int ly = R % w.bh, z = R / w.bh;
+  float4* out = w.band + ((long long)z * w.side + ly) * w.side;
+  for (int lx = lane; lx < w.bw; lx += 64) {
+    float f[kQ];
+    pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    drho += f[i];
-    jx += cxq(i) * f[i];
-    jy += cyq(i) * f[i];
-    jz += czq(i) * f[i];
-  }
-  const float rho = 1.0f + drho;
-  const float ux = (jx + 0.5f * a.p.fb[0]) / rho;
-  const float uy = (jy + 0.5f * a.p.fb[1]) / rho;
-  const float uz = (jz + 0.5f * a.p.fb[2]) / rho;
-  double s0 = Dw * (double)rho, s1 = Dw * (double)ux, s2 = Dw * (double)uy, s3 = Dw * (double)uz;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off);
-    s1 += __shfl_xor(s1, off);
-    s2 += __shfl_xor(s2, off);
-    s3 += __shfl_xor(s3, off);
-  }
-  if (lane == 0) {
-    const double Ux = vx - thd * ry, Uy = vy + thd * rx, Uz = 0.0;
-    a.X[3 * m] = X; a.X[3 * m + 1] = Y; a.X[3 * m + 2] = Z;
-    a.U[3 * m] = Ux; a.U[3 * m + 1] = Uy; a.U[3 * m + 2] = Uz;
-    a.rhoB[m] = s0;
-    a.B[3 * m] = Ux - s1;                 // Eq. 19: B = U_B - I u*
-    a.B[3 * m + 1] = Uy - s2;
-    a.B[3 * m + 2] = Uz - s3;
+    for (int i = 0; i < kQ; ++i) {
+      drho += f[i];
+      jx += cxq(i) * f[i];
+      jy += cyq(i) * f[i];
+      jz += czq(i) * f[i];
+    }
+    const float rho = 1.0f + drho;
+    out[lx] = make_float4(rho, (jx + 0.5f * a.p.fb[0]) / rho, (jy + 0.5f * a.p.fb[1]) / rho,
+                          (jz + 0.5f * a.p.fb[2]) / rho);
   }
 }
 
-// Block (foil w, span layer s): y = (M_xy^-1 (x) M_z^+) B restricted to the
-// n_p markers of layer s, du_B = y / dA, and the force/moment of the layer.
-__global__ void __launch_bounds__(256) k_solve(MarkerArgs a) {
-  __shared__ double Cs[kMaxPerim * 3];
-  __shared__ double red[4][256];
-  __shared__ int last;
-  int wi = 0, blk = blockIdx.x;
-  while (wi + 1 < a.nw && blk >= a.w[wi].ns) { blk -= a.w[wi].ns; ++wi; }
+__device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, int& wi) {
+  wi = 0;
+  while (wi + 1 < a.nw && blk >= a.w[wi].ns) {
+    blk -= a.w[wi].ns;
+    ++wi;
+  }
+  return blk;
+}
+
+// Block (foil, span layer s): for each perimeter marker p, one wave with a
+// lane per node of its 4x4x4 support interpolates rho and u* (Eq. 17) in
+// FP64, B = U_B - I u* (Eq. 19); then C[p] = sum_q M_xy^-1[p][q] B[q] for
+// the layer.  Marker X, U, rho_B and B are kept for the caller.  The
+// perimeter records and the inverse are staged in LDS first.
+__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double Bl[kMaxPerim * 3];
+  int wi;
+  const int s = find_layer_block(a, blockIdx.x, wi);
   const WingDev& w = a.w[wi];
-  const int s = blk, n = w.np, ns = w.ns;
-  const double* G = a.G + w.g_off;
-  // span convolution with the circulant pseudo-inverse row G
-  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
-    const int p = e / 3, comp = e - 3 * p;
-    const double* Bp = a.B + 3 * (size_t)(w.moff + p * ns) + comp;
-    double acc = 0.0;
-    for (int s2 = 0; s2 < ns; ++s2) {
-      int d = s - s2;
-      if (d < 0) d += ns;
-      acc += G[d] * Bp[3 * s2];
+  const int n = w.np, ns = w.ns;
+  double* P = lds;              // n * kPw
+  double* Mi = lds + n * kPw;   // n * n
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
+  __syncthreads();
+  double th, thd, hx, hy, vx, vy;
+  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
+  int zn = s - 1 + oz;
+  zn = zn < 0 ? zn + a.g.nz : (zn >= a.g.nz ? zn - a.g.nz : zn);
+  const float4* layer = w.band + (long long)zn * w.side * w.side;
+  const double wz = a.wz[oz];
+  // markers p = wave + 4 j, eight at a time: issue the eight band loads
+  // before the first reduction
+  constexpr int kChunk = 8;
+  for (int j0 = wave; j0 < n; j0 += 4 * kChunk) {
+    float4 v[kChunk];
+    double D[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int p = j0 + 4 * u;
+      if (p < n) {
+        const double* r = P + p * kPw;
+        const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+        v[u] = layer[ly * w.side + lx];
+        D[u] = r[4 + ox] * r[8 + oy] * wz;
+      }
     }
-    Cs[e] = acc;
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int p = j0 + 4 * u;
+      if (p >= n) break;
+      const double* r = P + p * kPw;
+      double s0 = D[u] * (double)v[u].x, s1 = D[u] * (double)v[u].y;
+      double s2 = D[u] * (double)v[u].z, s3 = D[u] * (double)v[u].w;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        s0 += __shfl_xor(s0, off);
+        s1 += __shfl_xor(s1, off);
+        s2 += __shfl_xor(s2, off);
+        s3 += __shfl_xor(s3, off);
+      }
+      if (lane == 0) {
+        const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+        const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
+        a.X[3 * m] = r[0];
+        a.X[3 * m + 1] = r[1];
+        a.X[3 * m + 2] = s + 0.5;
+        a.U[3 * m] = Ux;
+        a.U[3 * m + 1] = Uy;
+        a.U[3 * m + 2] = 0.0;
+        a.rhoB[m] = s0;
+        const double b0 = Ux - s1, b1 = Uy - s2, b2 = 0.0 - s3;   // Eq. 19: B = U_B - I u*
+        a.B[3 * m] = b0;
+        a.B[3 * m + 1] = b1;
+        a.B[3 * m + 2] = b2;
+        Bl[3 * p] = b0;
+        Bl[3 * p + 1] = b1;
+        Bl[3 * p + 2] = b2;
+      }
+    }
   }
   __syncthreads();
-  // perimeter inverse, then du_B and the per-marker body force -2 rho_B y
-  const double* Mi = a.Minv + w.minv_off;
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int p = e / 3, comp = e - 3 * p;
+    double acc = 0.0;
+    for (int q = 0; q < n; ++q) acc += Mi[p * n + q] * Bl[3 * q + comp];
+    a.C[w.c_off + ((size_t)p * 3 + comp) * ns + s] = acc;
+  }
+}
+
+// Block (foil, perimeter marker p): y = M_z^+ C along the span (circular
+// convolution with the pseudo-inverse row G), du_B = y / dA, and the force
+// and moment of the span column (Eq. 26: f_B = 2 rho_B du_B, body force
+// -f_B dA = -2 rho_B y), reduced in a fixed order.
+__global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[4][256];
+  int wi = 0, p = blockIdx.x;
+  while (wi + 1 < a.nw && p >= a.w[wi].np) {
+    p -= a.w[wi].np;
+    ++wi;
+  }
+  const WingDev& w = a.w[wi];
+  const int ns = w.ns;
+  double* G = lds;
+  double* Cc = lds + ns;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) G[i] = a.G[w.g_off + i];
+  const double* Cg = a.C + w.c_off + (size_t)p * 3 * ns;
+  for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Cc[i] = Cg[i];
+  __syncthreads();
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
   double fx = 0.0, fy = 0.0, fz = 0.0, mz = 0.0;
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    for (int q = 0; q < n; ++q) {
-      const double mv = Mi[p * n + q];
-      y0 += mv * Cs[3 * q];
-      y1 += mv * Cs[3 * q + 1];
-      y2 += mv * Cs[3 * q + 2];
-    }
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    const double r = a.rhoB[m], Xm = a.X[3 * m], Ym = a.X[3 * m + 1];
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    for (int s2 = 0; s2 <= s; ++s2) {
+      const double g = G[s - s2];
+      y0 += g * Cc[s2];
+      y1 += g * Cc[ns + s2];
+      y2 += g * Cc[2 * ns + s2];
+    }
+    for (int s2 = s + 1; s2 < ns; ++s2) {
+      const double g = G[s - s2 + ns];
+      y0 += g * Cc[s2];
+      y1 += g * Cc[ns + s2];
+      y2 += g * Cc[2 * ns + s2];
+    }
     a.duB[3 * m] = y0 / w.dA;
     a.duB[3 * m + 1] = y1 / w.dA;
     a.duB[3 * m + 2] = y2 / w.dA;
-    const double r = a.rhoB[m];
-    const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // Eq. 26, on the body
+    const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // on the body
     fx += bx;
     fy += by;
     fz += bz;
-    mz += (a.X[3 * m] - hx) * by - (a.X[3 * m + 1] - hy) * bx;
+    mz += (Xm - hx) * by - (Ym - hy) * bx;
   }
   red[0][threadIdx.x] = fx;
   red[1][threadIdx.x] = fy;
@@ -690,90 +778,126 @@ __global__ void __launch_bounds__(256) k_solve(MarkerArgs a) {
       for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
     __syncthreads();
   }
-  double* fp = a.fpart + 4 * ((size_t)w.layer_off + s);   // layer partials of this foil
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 4; ++k) fp[k] = red[k][0];
-    __threadfence();
-    const unsigned prev = atomicAdd(&a.counters[wi], 1u);
-    last = (prev == (unsigned)(ns - 1));
+  if (threadIdx.x < 4) w.fpart[4 * p + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Block per foil: sum of the span-column forces in a fixed order, then the
+// coefficients (Sec. 3.6-3.7): lift is the lateral component, counted
+// outward for a mirrored pair; thrust is -F_x; drag = -thrust.
+__global__ void __launch_bounds__(256) k_forces(MarkerArgs a) {
+  __shared__ double red[4][256];
+  const WingDev& w = a.w[blockIdx.x];
+  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = 0.0;
+  for (int q = threadIdx.x; q < w.np; q += blockDim.x)
+    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += w.fpart[4 * q + k];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double qS = 0.5 * a.u_ref * a.u_ref * a.area_ref;
+  double* h = a.hist + ((size_t)a.hist_row * a.nw + blockIdx.x) * 8;
+  const double F0 = red[0][0], F1 = red[1][0], F2 = red[2][0], F3 = red[3][0];
+  h[0] = F0;
+  h[1] = F1;
+  h[2] = F2;
+  h[3] = F3;
+  h[4] = -w.sense * F1 / qS;
+  h[5] = -F0 / qS;
+  h[6] = F0 / qS;
+  h[7] = F3 / (qS * w.chord);
+}
+
+// Block (foil, span layer s): the xy image of sum_p du_B D_xy dA over the
+// foil's box (Eq. 15 without the span factor, which the collide kernel
+// applies).  Inputs are staged in LDS; one wave then adds the markers in
+// perimeter order, so the sums are the same on every run.
+__global__ void __launch_bounds__(256) k_spread(MarkerArgs a) {
+  extern __shared__ double lds[];
+  int wi;
+  const int s = find_layer_block(a, blockIdx.x, wi);
+  const WingDev& w = a.w[wi];
+  const int n = w.np;
+  const int cells = w.bw * w.bh;
+  double* P = lds;                                   // n * kPw
+  double* Dv = P + n * kPw;                          // n * 3
+  float* img = reinterpret_cast<float*>(Dv + 3 * n); // cells * 3
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int p = e / 3, comp = e - 3 * p;
+    Dv[e] = a.duB[3 * ((size_t)w.moff + (size_t)p * w.ns + s) + comp];
+  }
+  for (int i = threadIdx.x; i < 3 * cells; i += blockDim.x) img[i] = 0.f;
+  __syncthreads();
+  if (threadIdx.x < 48) {
+    const int node = threadIdx.x % 16, comp = threadIdx.x / 16;
+    const int ox = node & 3, oy = node >> 2;
+    for (int p = 0; p < n; ++p) {
+      const double* r = P + p * kPw;
+      const double v = r[4 + ox] * r[8 + oy] * w.dA * Dv[3 * p + comp];
+      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+      img[3 * (ly * w.bw + lx) + comp] += (float)v;
+      __builtin_amdgcn_wave_barrier();
+    }
   }
   __syncthreads();
-  if (!last) return;
-  // last layer of this foil: fixed-order sum over layers -> history row
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const double* base = a.fpart + 4 * (size_t)w.layer_off;
-    double F[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l = 0; l < ns; ++l)
-      for (int k = 0; k < 4; ++k) F[k] += base[4 * l + k];
-    const double qS = 0.5 * a.u_ref * a.u_ref * a.area_ref;
-    double* h = a.hist + ((size_t)a.hist_row * a.nw + wi) * 8;
-    h[0] = F[0];
-    h[1] = F[1];
-    h[2] = F[2];
-    h[3] = F[3];
-    h[4] = -w.sense * F[1] / qS;    // lift: lateral, outward for a mirrored pair
-    h[5] = -F[0] / qS;              // thrust
-    h[6] = F[0] / qS;               // drag = -thrust
-    h[7] = F[3] / (qS * w.chord);
-    a.counters[wi] = 0u;
+  float4* out = w.corr + (size_t)s * w.side * w.side;
+  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+    const int ly = i / w.bw, lx = i - ly * w.bw;
+    out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
   }
 }
 
-// One wave per marker: du(x) += D dA du_B at each node of its support.
-__global__ void __launch_bounds__(256) k_spread(MarkerArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int m = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (m >= a.m_total) return;
-  const int wi = find_wing(a, m);
-  const WingDev& w = a.w[wi];
-  const double X = a.X[3 * m], Y = a.X[3 * m + 1], Z = a.X[3 * m + 2];
-  double wx[4], wy[4], wz[4];
-  const int bx = weights4(X, wx), by = weights4(Y, wy), bz = weights4(Z, wz);
-  const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-  const Geo& g = a.g;
-  const int nx = wrapi(bx + ox, g.nx, g.bclo == BC_PERIODIC);
-  const int ny = wrapi(by + oy, g.ny, g.yper);
-  const int nz = wrapi(bz + oz, g.nz, g.zper);
-  const double wgt = wx[ox] * wy[oy] * wz[oz] * w.dA;
-  const size_t N = (size_t)g.nx * g.ny * g.nz;
-  const size_t cell = ((size_t)nz * g.ny + ny) * g.nx + nx;
-  if (wgt != 0.0) {
-    unsafeAtomicAdd(a.du + cell, (float)(wgt * a.duB[3 * m]));
-    unsafeAtomicAdd(a.du + N + cell, (float)(wgt * a.duB[3 * m + 1]));
-    unsafeAtomicAdd(a.du + 2 * N + cell, (float)(wgt * a.duB[3 * m + 2]));
-  }
-  const int tile = ((nz >> 3) * a.tny + (ny >> 3)) * a.tnx + (nx >> 3);
-  a.stamps[tile] = a.stamp;
+static hipError_t raise_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s) {
+  int maxnp = 0;
+  for (int k = 0; k < a.nw; ++k) maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+  const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double);
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_factor), lds);
+  if (e != hipSuccess) return e;
+  k_factor<<<(unsigned)(count * a.nw), 256, lds, s>>>(a);
+  return hipGetLastError();
 }
 
 hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
-  int maxnp = 0, nlayers = 0;
+  int maxnp = 0, layers = 0, perims = 0, maxcells = 0, ns = a.g.nz;
   for (int k = 0; k < a.nw; ++k) {
     maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
-    nlayers += a.w[k].ns;
+    layers += a.w[k].ns;
+    perims += a.w[k].np;
+    const int c = a.w[k].bw * a.w[k].bh;
+    maxcells = c > maxcells ? c : maxcells;
   }
-  const size_t lds = ((size_t)maxnp * maxnp + 2 * (size_t)maxnp) * sizeof(double);
-  if (lds > 65536) {
-    hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(k_factor),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (ea != hipSuccess) return ea;
-  }
-  k_factor<<<a.nw, 256, lds, s>>>(a);
-  hipError_t e = hipGetLastError();
+  const size_t lds_i = ((size_t)maxnp * maxnp + (size_t)kPw * maxnp) * sizeof(double);
+  const size_t lds_s = ((size_t)(kPw + 3) * maxnp) * sizeof(double) + (size_t)maxcells * 3 * sizeof(float);
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_spread), lds_s);
   if (e != hipSuccess) return e;
-  const unsigned nbm = (unsigned)((a.m_total + 3) / 4);
+  const unsigned nb = (unsigned)a.band_blocks;   // 4 box rows per block
   switch (storage) {
-    case ST_F32: k_interp<StF32><<<nbm, 256, 0, s>>>(a); break;
-    case ST_F16: k_interp<StF16><<<nbm, 256, 0, s>>>(a); break;
-    default: k_interp<StBF16><<<nbm, 256, 0, s>>>(a); break;
+    case ST_F32: k_band<StF32><<<nb, 256, 0, s>>>(a); break;
+    case ST_F16: k_band<StF16><<<nb, 256, 0, s>>>(a); break;
+    default: k_band<StBF16><<<nb, 256, 0, s>>>(a); break;
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_solve<<<nlayers, 256, 0, s>>>(a);
+  k_interp<<<layers, 256, lds_i, s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_spread<<<nbm, 256, 0, s>>>(a);
+  k_span<<<perims, 256, 4 * (size_t)ns * sizeof(double), s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_forces<<<a.nw, 256, 0, s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_spread<<<layers, 256, lds_s, s>>>(a);
   return hipGetLastError();
 }
 

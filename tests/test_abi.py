@@ -123,3 +123,10 @@ def test_solver_refuses_without_gpu():
     bx, wg = _plate()
     with pytest.raises(RuntimeError):
         Solver(bx, wg)
+
+
+def test_single_hip_runtime_after_load():
+    L, lib = _lib()
+    import torch  # noqa: F401
+    rts = L._hip_runtimes()
+    assert len(rts) <= 1, rts

@@ -81,24 +81,38 @@ def plate_case(nx=64, ny=32, nz=32, chord=10.0, aspect=5.0, u_inf=0.02, re=100.0
     return bx, wg, phys
 
 
+def clap_gap(chord, aspect=5.0):
+    """Distance between the two chord lines at the hinges.
+
+    The paper takes c/2, chosen so that the lattice nodes around the markers
+    of one foil do not interact with the other (Sec. 3.3).  With the 4-point
+    kernel that needs the facing surfaces (chord lines less one thickness)
+    at least 4 cells apart; for short chords c/2 is too small, so the gap is
+    max(c/2, thickness + 5).  At chord 20 and above this is c/2.
+    """
+    return max(0.5 * chord, chord / aspect + 5.0)
+
+
 def clap_fling_case(nx=256, ny=192, nz=192, chord=20.0, aspect=5.0,
                     re=100.0, j=0.01, f=0.25):
-    """Two foils hinged at their trailing edges, gap c/2, clap & fling.
+    """Two foils hinged at their trailing edges, clap & fling.
 
     alpha(t) = (pi/3)|sin(2 pi t / T)|; the upper foil turns with sense -1 and
     the lower with +1 so both leading edges open outward.  Hinges at
-    x = 3 nx / 8 and y = ny/2 - 1/2 +- c/4 (mirror plane between cell rows).
-    Flow parameters are returned raw in `physics`; the solver maps them.
+    x = 3 nx / 8 and y = ny/2 - 1/2 +- gap/2 (mirror plane between cell
+    rows), gap = clap_gap(chord).  Flow parameters are returned raw in
+    `physics`; the solver maps them.
     """
     phys = dict(kind="clap_fling", re=re, j=j, f=f, chord=chord, kappa=KAPPA)
     xh = 3.0 * nx / 8.0
     ymid = ny / 2.0 - 0.5
+    half = 0.5 * clap_gap(chord, aspect)
     bx = dict(nx=nx, ny=ny, nz=nz,
               bc=[VELOCITY, PRESSURE, WALL, WALL, PERIODIC, PERIODIC],
               u_in=None, rho_out=1.0, body_force=[0.0, 0.0, 0.0],
               u_ref=None, area_ref=chord * nz)
     wg = []
-    for sense, yh in ((-1.0, ymid + chord / 4.0), (1.0, ymid - chord / 4.0)):
+    for sense, yh in ((-1.0, ymid + half), (1.0, ymid - half)):
         # period_steps is left None: it follows from (f, chord) through the
         # lattice mapping, which each solver side computes itself
         wg.append(wing(chord, chord / aspect, (xh, yh), 1.0, 0.0, sense,
