@@ -166,10 +166,12 @@ IBMLBM_API int32_t ibmlbm_marker_count(ibmlbm_t h);
  * if none yet.  Returns EDIVERGED once a check has seen a non-finite value. */
 IBMLBM_API int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass);
 
-/* Kernel timing: with enable = 1 every later collide-stream launch is
- * bracketed by HIP events on the handle's stream; read_timing synchronises,
- * returns the summed milliseconds and launch count of those kernels and of
- * the marker kernels, and resets the sums.  enable = 0 stops recording. */
+/* Kernel timing: with enable = k > 0 the collide-stream launch and the
+ * marker kernels of every k-th step are bracketed by HIP events (recorded
+ * without a system-scope fence) on the handle's stream; read_timing
+ * synchronises, returns the summed milliseconds and count of the bracketed
+ * collide launches and the summed marker milliseconds, and resets the sums.
+ * enable = 0 stops recording. */
 IBMLBM_API int ibmlbm_timing(ibmlbm_t h, int32_t enable);
 IBMLBM_API int ibmlbm_read_timing(ibmlbm_t h, double* collide_ms, int64_t* collide_launches,
                        double* marker_ms);

@@ -77,6 +77,7 @@ struct ibmlbm_s {
   long long win_t0 = -1;            // window of precomputed perimeter factors
   // timing
   bool timing = false;
+  int timing_every = 1;             // bracket one step in this many
   std::vector<hipEvent_t> ev;       // pairs: start, stop
   std::vector<int> ev_kind;         // 0 = collide, 1 = markers
   size_t ev_used = 0;
@@ -497,7 +498,7 @@ void fill_phys(ibmlbm_t h) {
 }
 
 int record_event(ibmlbm_t h, int kind, bool start) {
-  if (!h->timing) return IBMLBM_OK;
+  if (!h->timing || h->step % h->timing_every != 0) return IBMLBM_OK;
   if (start) {
     if (h->ev_used + 2 > h->ev.size()) {
       // pool full: fold the recorded pairs into the sums first
@@ -913,7 +914,8 @@ int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
     // no system-scope fence: the events only time kernels on this device
     for (auto& e : h->ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
-  h->timing = enable != 0;
+  h->timing = enable > 0;
+  h->timing_every = enable > 0 ? enable : 1;
   return IBMLBM_OK;
 }
 

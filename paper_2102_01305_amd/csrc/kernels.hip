@@ -11,8 +11,8 @@
 //            B = U_B - I u* (Eq. 19), then the perimeter solve per layer.
 //  span      the span part of the minimum-norm solve (Eq. 19), du_B, and the
 //            force and moment of each span column (Eq. 26).
-//  forces    per foil: fixed-order sum of the columns, coefficients, history.
-//  spread    sum_l du_B D dA over each layer of each foil's box (Eq. 15).
+//  spread    sum_l du_B D dA over each layer of each foil's box (Eq. 15);
+//            the fixed-order force sum and coefficients of each foil.
 //
 // Distributions are stored as deviations from the lattice weights,
 // f~_i = f_i - w_i, so FP32 (and 16-bit) storage keeps the small velocity
@@ -625,27 +625,35 @@ __global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
   }
 }
 
-__device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, int& wi) {
+// Blocks that work on span layers take kLayerPair of them at once, one
+// 256-thread half-block per layer; block b covers layers 2 j, 2 j + 1 of a foil.
+constexpr int kLayerPair = 2;
+
+__device__ __forceinline__ int find_pair_block(const MarkerArgs& a, int blk, int& wi) {
   wi = 0;
-  while (wi + 1 < a.nw && blk >= a.w[wi].ns) {
-    blk -= a.w[wi].ns;
+  while (wi + 1 < a.nw) {
+    const int pairs = (a.w[wi].ns + kLayerPair - 1) / kLayerPair;
+    if (blk < pairs) break;
+    blk -= pairs;
     ++wi;
   }
   return blk;
 }
 
-// Block (foil, span layer s): for each perimeter marker p, one wave with a
-// lane per node of its 4x4x4 support interpolates rho and u* (Eq. 17) in
-// FP64, B = U_B - I u* (Eq. 19); then C[p] = sum_q M_xy^-1[p][q] B[q] for
-// the layer.  Marker X, U, rho_B and B are kept for the caller.  The
-// perimeter records and the inverse are staged in LDS first.
-__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
+// Block (foil, pair of span layers): for each perimeter marker p, one wave
+// with a lane per node of its 4x4x4 support interpolates rho and u*
+// (Eq. 17) in FP64, B = U_B - I u* (Eq. 19); then C[p] = sum_q
+// M_xy^-1[p][q] B[q] for the layer.  Marker X, U, rho_B and B are kept for
+// the caller.  The perimeter records and the inverse are staged in LDS.
+__global__ void __launch_bounds__(512) k_interp(MarkerArgs a) {
   extern __shared__ double lds[];
-  __shared__ double Bl[kMaxPerim * 3];
+  __shared__ double Bl[kLayerPair][kMaxPerim * 3];
   int wi;
-  const int s = find_layer_block(a, blockIdx.x, wi);
+  const int pair = find_pair_block(a, blockIdx.x, wi);
   const WingDev& w = a.w[wi];
   const int n = w.np, ns = w.ns;
+  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int s = pair * kLayerPair + half;
   double* P = lds;              // n * kPw
   double* Mi = lds + n * kPw;   // n * n
   const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
@@ -655,68 +663,76 @@ __global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
   __syncthreads();
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = tid >> 6, lane = tid & 63;
   const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-  int zn = s - 1 + oz;
-  zn = zn < 0 ? zn + a.g.nz : (zn >= a.g.nz ? zn - a.g.nz : zn);
-  const float4* layer = w.band + (long long)zn * w.side * w.side;
-  const double wz = a.wz[oz];
-  // markers p = wave + 4 j, eight at a time: issue the eight band loads
-  // before the first reduction
-  constexpr int kChunk = 8;
-  for (int j0 = wave; j0 < n; j0 += 4 * kChunk) {
-    float4 v[kChunk];
-    double D[kChunk];
+  if (s < ns) {
+    int zn = s - 1 + oz;
+    zn = zn < 0 ? zn + a.g.nz : (zn >= a.g.nz ? zn - a.g.nz : zn);
+    const float4* layer = w.band + (long long)zn * w.side * w.side;
+    const double wz = a.wz[oz];
+    // markers p = wave + 4 j, eight at a time: issue the eight band loads
+    // before the first reduction
+    constexpr int kChunk = 8;
+    for (int j0 = wave; j0 < n; j0 += 4 * kChunk) {
+      float4 v[kChunk];
+      double D[kChunk];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int p = j0 + 4 * u;
-      if (p < n) {
+      for (int u = 0; u < kChunk; ++u) {
+        const int p = j0 + 4 * u;
+        if (p < n) {
+          const double* r = P + p * kPw;
+          const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+          v[u] = layer[ly * w.side + lx];
+          D[u] = r[4 + ox] * r[8 + oy] * wz;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const int p = j0 + 4 * u;
+        if (p >= n) break;
         const double* r = P + p * kPw;
-        const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
-        v[u] = layer[ly * w.side + lx];
-        D[u] = r[4 + ox] * r[8 + oy] * wz;
-      }
-    }
+        double s0 = D[u] * (double)v[u].x, s1 = D[u] * (double)v[u].y;
+        double s2 = D[u] * (double)v[u].z, s3 = D[u] * (double)v[u].w;
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int p = j0 + 4 * u;
-      if (p >= n) break;
-      const double* r = P + p * kPw;
-      double s0 = D[u] * (double)v[u].x, s1 = D[u] * (double)v[u].y;
-      double s2 = D[u] * (double)v[u].z, s3 = D[u] * (double)v[u].w;
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        s0 += __shfl_xor(s0, off);
-        s1 += __shfl_xor(s1, off);
-        s2 += __shfl_xor(s2, off);
-        s3 += __shfl_xor(s3, off);
-      }
-      if (lane == 0) {
-        const size_t m = (size_t)w.moff + (size_t)p * ns + s;
-        const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
-        a.X[3 * m] = r[0];
-        a.X[3 * m + 1] = r[1];
-        a.X[3 * m + 2] = s + 0.5;
-        a.U[3 * m] = Ux;
-        a.U[3 * m + 1] = Uy;
-        a.U[3 * m + 2] = 0.0;
-        a.rhoB[m] = s0;
-        const double b0 = Ux - s1, b1 = Uy - s2, b2 = 0.0 - s3;   // Eq. 19: B = U_B - I u*
-        a.B[3 * m] = b0;
-        a.B[3 * m + 1] = b1;
-        a.B[3 * m + 2] = b2;
-        Bl[3 * p] = b0;
-        Bl[3 * p + 1] = b1;
-        Bl[3 * p + 2] = b2;
+        for (int off = 32; off > 0; off >>= 1) {
+          s0 += __shfl_xor(s0, off);
+          s1 += __shfl_xor(s1, off);
+          s2 += __shfl_xor(s2, off);
+          s3 += __shfl_xor(s3, off);
+        }
+        if (lane == 0) {
+          const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+          const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
+          a.X[3 * m] = r[0];
+          a.X[3 * m + 1] = r[1];
+          a.X[3 * m + 2] = s + 0.5;
+          a.U[3 * m] = Ux;
+          a.U[3 * m + 1] = Uy;
+          a.U[3 * m + 2] = 0.0;
+          a.rhoB[m] = s0;
+          const double b0 = Ux - s1, b1 = Uy - s2, b2 = 0.0 - s3;   // Eq. 19: B = U_B - I u*
+          a.B[3 * m] = b0;
+          a.B[3 * m + 1] = b1;
+          a.B[3 * m + 2] = b2;
+          Bl[half][3 * p] = b0;
+          Bl[half][3 * p + 1] = b1;
+          Bl[half][3 * p + 2] = b2;
+        }
       }
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+  if (s >= ns) return;
+  for (int e = tid; e < 3 * n; e += 256) {
     const int p = e / 3, comp = e - 3 * p;
-    double acc = 0.0;
-    for (int q = 0; q < n; ++q) acc += Mi[p * n + q] * Bl[3 * q + comp];
-    a.C[w.c_off + ((size_t)p * 3 + comp) * ns + s] = acc;
+    double acc0 = 0.0, acc1 = 0.0;
+    int q = 0;
+    for (; q + 1 < n; q += 2) {
+      acc0 += Mi[p * n + q] * Bl[half][3 * q + comp];
+      acc1 += Mi[p * n + q + 1] * Bl[half][3 * (q + 1) + comp];
+    }
+    if (q < n) acc0 += Mi[p * n + q] * Bl[half][3 * q + comp];
+    a.C[w.c_off + ((size_t)p * 3 + comp) * ns + s] = acc0 + acc1;
   }
 }
 
@@ -746,18 +762,44 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   for (int s = threadIdx.x; s < ns; s += blockDim.x) {
     const size_t m = (size_t)w.moff + (size_t)p * ns + s;
     const double r = a.rhoB[m], Xm = a.X[3 * m], Ym = a.X[3 * m + 1];
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    for (int s2 = 0; s2 <= s; ++s2) {
-      const double g = G[s - s2];
-      y0 += g * Cc[s2];
-      y1 += g * Cc[ns + s2];
-      y2 += g * Cc[2 * ns + s2];
-    }
-    for (int s2 = s + 1; s2 < ns; ++s2) {
-      const double g = G[s - s2 + ns];
-      y0 += g * Cc[s2];
-      y1 += g * Cc[ns + s2];
-      y2 += g * Cc[2 * ns + s2];
+    // y_c(s) = sum_s2 G[(s - s2) mod ns] C_c[s2], in two halves without the
+    // modulo, eight terms at a time into split accumulators
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
+    {
+      int s2 = 0;
+      for (; s2 + 1 <= s; s2 += 2) {
+        const double g = G[s - s2], h = G[s - s2 - 1];
+        y0 += g * Cc[s2];
+        y1 += g * Cc[ns + s2];
+        y2 += g * Cc[2 * ns + s2];
+        z0 += h * Cc[s2 + 1];
+        z1 += h * Cc[ns + s2 + 1];
+        z2 += h * Cc[2 * ns + s2 + 1];
+      }
+      for (; s2 <= s; ++s2) {
+        const double g = G[s - s2];
+        y0 += g * Cc[s2];
+        y1 += g * Cc[ns + s2];
+        y2 += g * Cc[2 * ns + s2];
+      }
+      for (; s2 + 1 < ns; s2 += 2) {
+        const double g = G[s - s2 + ns], h = G[s - s2 - 1 + ns];
+        y0 += g * Cc[s2];
+        y1 += g * Cc[ns + s2];
+        y2 += g * Cc[2 * ns + s2];
+        z0 += h * Cc[s2 + 1];
+        z1 += h * Cc[ns + s2 + 1];
+        z2 += h * Cc[2 * ns + s2 + 1];
+      }
+      for (; s2 < ns; ++s2) {
+        const double g = G[s - s2 + ns];
+        y0 += g * Cc[s2];
+        y1 += g * Cc[ns + s2];
+        y2 += g * Cc[2 * ns + s2];
+      }
+      y0 += z0;
+      y1 += z1;
+      y2 += z2;
     }
     a.duB[3 * m] = y0 / w.dA;
     a.duB[3 * m + 1] = y1 / w.dA;
@@ -781,24 +823,69 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   if (threadIdx.x < 4) w.fpart[4 * p + threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Block per foil: sum of the span-column forces in a fixed order, then the
-// coefficients (Sec. 3.6-3.7): lift is the lateral component, counted
-// outward for a mirrored pair; thrust is -F_x; drag = -thrust.
-__global__ void __launch_bounds__(256) k_forces(MarkerArgs a) {
-  __shared__ double red[4][256];
-  const WingDev& w = a.w[blockIdx.x];
+// Block (foil, pair of span layers): the xy image of sum_p du_B D_xy dA over
+// the foil's box (Eq. 15 without the span factor, which the collide kernel
+// applies).  Inputs are staged in LDS; one wave per layer then adds the
+// markers in perimeter order, so the sums are the same on every run.  The
+// first block of each foil also sums the span-column forces in a fixed
+// order and writes the coefficients (Sec. 3.6-3.7): lift is the lateral
+// component, counted outward for a mirrored pair; thrust is -F_x; drag is
+// -thrust.
+__global__ void __launch_bounds__(512) k_spread(MarkerArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[4][512];
+  int wi;
+  const int pair = find_pair_block(a, blockIdx.x, wi);
+  const WingDev& w = a.w[wi];
+  const int n = w.np;
+  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
+  const int s = pair * kLayerPair + half;
+  const int cells = w.bw * w.bh;
+  double* P = lds;                                        // n * kPw
+  double* Dv = P + n * kPw;                               // 2 * n * 3
+  float* img = reinterpret_cast<float*>(Dv + 6 * n) + half * 3 * cells;
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  if (s < w.ns)
+    for (int e = tid; e < 3 * n; e += 256) {
+      const int p = e / 3, comp = e - 3 * p;
+      Dv[half * 3 * n + e] = a.duB[3 * ((size_t)w.moff + (size_t)p * w.ns + s) + comp];
+    }
+  for (int i = tid; i < 3 * cells; i += 256) img[i] = 0.f;
+  __syncthreads();
+  if (s < w.ns && tid < 48) {
+    const int node = tid % 16, comp = tid / 16;
+    const int ox = node & 3, oy = node >> 2;
+    const double* D = Dv + half * 3 * n;
+    for (int p = 0; p < n; ++p) {
+      const double* r = P + p * kPw;
+      const double v = r[4 + ox] * r[8 + oy] * w.dA * D[3 * p + comp];
+      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+      img[3 * (ly * w.bw + lx) + comp] += (float)v;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  if (s < w.ns) {
+    float4* out = w.corr + (size_t)s * w.side * w.side;
+    for (int i = tid; i < cells; i += 256) {
+      const int ly = i / w.bw, lx = i - ly * w.bw;
+      out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
+    }
+  }
+  if (pair != 0) return;
   for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = 0.0;
-  for (int q = threadIdx.x; q < w.np; q += blockDim.x)
+  for (int q = threadIdx.x; q < n; q += blockDim.x)
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += w.fpart[4 * q + k];
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
+  for (int h = 256; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h)
       for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
   const double qS = 0.5 * a.u_ref * a.u_ref * a.area_ref;
-  double* h = a.hist + ((size_t)a.hist_row * a.nw + blockIdx.x) * 8;
+  double* h = a.hist + ((size_t)a.hist_row * a.nw + wi) * 8;
   const double F0 = red[0][0], F1 = red[1][0], F2 = red[2][0], F3 = red[3][0];
   h[0] = F0;
   h[1] = F1;
@@ -808,47 +895,6 @@ __global__ void __launch_bounds__(256) k_forces(MarkerArgs a) {
   h[5] = -F0 / qS;
   h[6] = F0 / qS;
   h[7] = F3 / (qS * w.chord);
-}
-
-// Block (foil, span layer s): the xy image of sum_p du_B D_xy dA over the
-// foil's box (Eq. 15 without the span factor, which the collide kernel
-// applies).  Inputs are staged in LDS; one wave then adds the markers in
-// perimeter order, so the sums are the same on every run.
-__global__ void __launch_bounds__(256) k_spread(MarkerArgs a) {
-  extern __shared__ double lds[];
-  int wi;
-  const int s = find_layer_block(a, blockIdx.x, wi);
-  const WingDev& w = a.w[wi];
-  const int n = w.np;
-  const int cells = w.bw * w.bh;
-  double* P = lds;                                   // n * kPw
-  double* Dv = P + n * kPw;                          // n * 3
-  float* img = reinterpret_cast<float*>(Dv + 3 * n); // cells * 3
-  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
-  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
-  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
-    const int p = e / 3, comp = e - 3 * p;
-    Dv[e] = a.duB[3 * ((size_t)w.moff + (size_t)p * w.ns + s) + comp];
-  }
-  for (int i = threadIdx.x; i < 3 * cells; i += blockDim.x) img[i] = 0.f;
-  __syncthreads();
-  if (threadIdx.x < 48) {
-    const int node = threadIdx.x % 16, comp = threadIdx.x / 16;
-    const int ox = node & 3, oy = node >> 2;
-    for (int p = 0; p < n; ++p) {
-      const double* r = P + p * kPw;
-      const double v = r[4 + ox] * r[8 + oy] * w.dA * Dv[3 * p + comp];
-      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
-      img[3 * (ly * w.bw + lx) + comp] += (float)v;
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
-  float4* out = w.corr + (size_t)s * w.side * w.side;
-  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
-    const int ly = i / w.bw, lx = i - ly * w.bw;
-    out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
-  }
 }
 
 static hipError_t raise_lds(const void* fn, size_t bytes) {
@@ -867,16 +913,17 @@ hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s) {
 }
 
 hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
-  int maxnp = 0, layers = 0, perims = 0, maxcells = 0, ns = a.g.nz;
+  int maxnp = 0, pairs = 0, perims = 0, maxcells = 0, ns = a.g.nz;
   for (int k = 0; k < a.nw; ++k) {
     maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
-    layers += a.w[k].ns;
+    pairs += (a.w[k].ns + kLayerPair - 1) / kLayerPair;
     perims += a.w[k].np;
     const int c = a.w[k].bw * a.w[k].bh;
     maxcells = c > maxcells ? c : maxcells;
   }
   const size_t lds_i = ((size_t)maxnp * maxnp + (size_t)kPw * maxnp) * sizeof(double);
-  const size_t lds_s = ((size_t)(kPw + 3) * maxnp) * sizeof(double) + (size_t)maxcells * 3 * sizeof(float);
+  const size_t lds_s = ((size_t)(kPw + 6) * maxnp) * sizeof(double) +
+                       (size_t)kLayerPair * maxcells * 3 * sizeof(float);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_spread), lds_s);
   if (e != hipSuccess) return e;
@@ -888,16 +935,13 @@ hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_interp<<<layers, 256, lds_i, s>>>(a);
+  k_interp<<<pairs, 512, lds_i, s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_span<<<perims, 256, 4 * (size_t)ns * sizeof(double), s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_forces<<<a.nw, 256, 0, s>>>(a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_spread<<<layers, 256, lds_s, s>>>(a);
+  k_spread<<<pairs, 512, lds_s, s>>>(a);
   return hipGetLastError();
 }
 

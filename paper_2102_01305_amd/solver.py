@@ -169,8 +169,9 @@ class Solver:
         return int(st.value), float(m.value)
 
     # -- timing --------------------------------------------------------------
-    def enable_timing(self, on=True):
-        L.check(self.lib.ibmlbm_timing(self.h, 1 if on else 0), self.h)
+    def enable_timing(self, every=1):
+        """Bracket the kernels of one step in `every` with HIP events (0 = off)."""
+        L.check(self.lib.ibmlbm_timing(self.h, int(every)), self.h)
 
     def read_timing(self):
         c = C.c_double()
