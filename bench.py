@@ -121,8 +121,10 @@ def main():
 
     mlups = N * args.steps / dt / 1e6
     bpc = 2 * 19 * (4 if args.storage == "fp32" else 2)
-    k6_ms = tim["collide_ms"] / tim["collide_launches"] if tim["collide_launches"] else float("nan")
-    achieved = bpc * N / (k6_ms * 1e-3) / 1e9 if tim["collide_launches"] else float("nan")
+    nl = tim["collide_launches"]
+    k6_ms = tim["collide_ms"] / nl if nl else float("nan")
+    cells_per_launch = tim["collide_cells"] / nl if nl else float("nan")
+    achieved = bpc * cells_per_launch / (k6_ms * 1e-3) / 1e9 if nl else float("nan")
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -142,7 +144,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_collide", "kernel_ms": round(k6_ms, 5),
-                     "bytes_per_cell": bpc,
+                     "bytes_per_cell": bpc, "cells_per_launch": cells_per_launch,
                      "timed_launches": tim["collide_launches"],
                      "marker_ms_per_step": round(tim["marker_ms"] / max(tim["collide_launches"], 1), 5)},
         "hbm_frac_whole_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),

@@ -61,7 +61,7 @@ SIGNATURES = [
     ("ibmlbm_marker_count", C.c_int32, [Handle]),
     ("ibmlbm_mass", C.c_int, [Handle, C.POINTER(C.c_int64), _dp]),
     ("ibmlbm_timing", C.c_int, [Handle, C.c_int32]),
-    ("ibmlbm_read_timing", C.c_int, [Handle, _dp, C.POINTER(C.c_int64), _dp]),
+    ("ibmlbm_read_timing", C.c_int, [Handle, _dp, C.POINTER(C.c_int64), _dp, _dp]),
     ("ibmlbm_bytes_per_cell", C.c_int32, [Handle]),
     ("ibmlbm_destroy", C.c_int, [Handle]),
     ("ibmlbm_last_error", C.c_char_p, [Handle]),

@@ -59,6 +59,8 @@ struct MarkerLayout {
 struct ibmlbm_s {
   ibmlbm_config cfg{};
   hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;        // marker kernels, overlapped with the bulk collide
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   LatticeLayout L;
@@ -81,7 +83,8 @@ struct ibmlbm_s {
   std::vector<hipEvent_t> ev;       // pairs: start, stop
   std::vector<int> ev_kind;         // 0 = collide, 1 = markers
   size_t ev_used = 0;
-  double acc_collide_ms = 0.0, acc_marker_ms = 0.0;
+  std::vector<double> ev_cells;      // cells updated by each timed collide launch
+  double acc_collide_ms = 0.0, acc_marker_ms = 0.0, acc_collide_cells = 0.0;
   long long acc_collide_n = 0;
   std::string err;
 };
@@ -497,23 +500,37 @@ void fill_phys(ibmlbm_t h) {
   h->phys.rho_out = (float)c.rho_out;
 }
 
-int record_event(ibmlbm_t h, int kind, bool start) {
+// Fold the recorded event pairs into the timing sums.
+int fold_events(ibmlbm_t h) {
+  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+    if (h->ev_kind[k / 2] == 0) {
+      h->acc_collide_ms += ms;
+      h->acc_collide_n++;
+      h->acc_collide_cells += h->ev_cells[k / 2];
+    } else {
+      h->acc_marker_ms += ms;
+    }
+  }
+  h->ev_used = 0;
+  return IBMLBM_OK;
+}
+
+// Timing event on stream `st` for the step being enqueued (kind 0: a
+// collide launch updating `cells` cells, kind 1: the marker kernels).
+int record_event(ibmlbm_t h, hipStream_t st, int kind, bool start, double cells = 0.0) {
   if (!h->timing || h->step % h->timing_every != 0) return IBMLBM_OK;
   if (start) {
     if (h->ev_used + 2 > h->ev.size()) {
-      // pool full: fold the recorded pairs into the sums first
       HIP_TRY(h, hipStreamSynchronize(h->stream));
-      for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
-        float ms = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
-        if (h->ev_kind[k / 2] == 0) { h->acc_collide_ms += ms; h->acc_collide_n++; }
-        else h->acc_marker_ms += ms;
-      }
-      h->ev_used = 0;
+      int rc = fold_events(h);
+      if (rc) return rc;
     }
     h->ev_kind[h->ev_used / 2] = kind;
+    h->ev_cells[h->ev_used / 2] = cells;
   }
-  HIP_TRY(h, hipEventRecord(h->ev[h->ev_used], h->stream));
+  HIP_TRY(h, hipEventRecord(h->ev[h->ev_used], st));
   h->ev_used++;
   return IBMLBM_OK;
 }
@@ -560,11 +577,15 @@ int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, v
   h->geo.bclo = cfg->bc[0];
   h->geo.bchi = cfg->bc[1];
   fill_phys(h);
-  hipError_t e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
+  hipError_t e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+  // fork/join events order kernels of one device: no system-scope fence
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming | hipEventDisableSystemFence);
+  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
-    int r = fail(nullptr, IBMLBM_EDEVICE, "workspace clear failed: %s", hipGetErrorString(e));
-    delete h;
+    int r = fail(nullptr, IBMLBM_EDEVICE, "create failed: %s", hipGetErrorString(e));
+    ibmlbm_destroy(h);
     return r;
   }
   *out = h;
@@ -740,11 +761,11 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
   }
   for (int k = 0; k < n; ++k) {
     const long long s = h->step;
+    bool need_factor = false;
     if (ibm) {
       if (h->win_t0 < 0 || s < h->win_t0 || s >= h->win_t0 + kFactorWindow) {
         h->win_t0 = s;
-        ma.win_t0 = s;
-        HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
+        need_factor = true;
       }
       ma.win_t0 = h->win_t0;
       ma.slot = (int)(s - h->win_t0);
@@ -765,20 +786,49 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
       long long box_rows = 0;
       for (int w = 0; w < h->nw; ++w) box_rows += (long long)ma.w[w].bh * c.nz;
       ma.band_blocks = (int)((box_rows + 3) / 4);
-      int rc = record_event(h, 1, true);
-      if (rc) return rc;
-      HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
-      rc = record_event(h, 1, false);
-      if (rc) return rc;
     }
     ca.src = cur_state(h);
     ca.dst = next_state(h);
     const bool check = c.check_interval > 0 && ((s + 1) % c.check_interval == 0);
-    int rc = record_event(h, 0, true);
-    if (rc) return rc;
-    HIP_TRY(h, launch_collide(c.storage, ibm, force, check, ca, h->stream));
-    rc = record_event(h, 0, false);
-    if (rc) return rc;
+    if (ibm && !check) {
+      // The marker kernels and then the update of the foil-box cells run on
+      // the auxiliary stream while the caller's stream updates every cell
+      // outside the boxes.  Both read S^n and write disjoint cells of
+      // S^(n+1); the caller's stream joins the auxiliary one before the
+      // next step, and the next step's marker kernels start after that.
+      long long box_cells = 0;
+      for (int w = 0; w < h->nw; ++w) box_cells += (long long)ca.box[w].w * ca.box[w].h * c.nz;
+      HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
+      HIP_TRY(h, hipStreamWaitEvent(h->aux, h->ev_fork, 0));
+      int rc = record_event(h, h->aux, 1, true);
+      if (rc) return rc;
+      if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->aux));
+      HIP_TRY(h, launch_markers(c.storage, ma, h->aux));
+      rc = record_event(h, h->aux, 1, false);
+      if (rc) return rc;
+      HIP_TRY(h, launch_collide(c.storage, COLLIDE_BOX, true, force, false, ca, h->aux));
+      HIP_TRY(h, hipEventRecord(h->ev_join, h->aux));
+      rc = record_event(h, h->stream, 0, true, (double)L.N - (double)box_cells);
+      if (rc) return rc;
+      HIP_TRY(h, launch_collide(c.storage, COLLIDE_BULK, false, force, false, ca, h->stream));
+      rc = record_event(h, h->stream, 0, false);
+      if (rc) return rc;
+      HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
+    } else {
+      if (ibm) {
+        int rc = record_event(h, h->stream, 1, true);
+        if (rc) return rc;
+        if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
+        HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
+        rc = record_event(h, h->stream, 1, false);
+        if (rc) return rc;
+      }
+      int rc = record_event(h, h->stream, 0, true, (double)L.N);
+      if (rc) return rc;
+      HIP_TRY(h, launch_collide(c.storage, COLLIDE_ALL, ibm, force, check, ca, h->stream));
+      rc = record_event(h, h->stream, 0, false);
+      if (rc) return rc;
+    }
     if (check)
       HIP_TRY(h, launch_mass_reduce(ca.mass_part, L.nblocks, (double)L.N,
                                     reinterpret_cast<double*>(h->ws + L.diag.off), s + 1, h->stream));
@@ -907,10 +957,11 @@ int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass) {
 
 int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
   if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
-  if (enable && h->ev.empty()) {
+  if (enable > 0 && h->ev.empty()) {
     const int pairs = 4096;
     h->ev.resize(2 * pairs);
     h->ev_kind.assign(pairs, 0);
+    h->ev_cells.assign(pairs, 0.0);
     // no system-scope fence: the events only time kernels on this device
     for (auto& e : h->ev) HIP_TRY(h, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
   }
@@ -919,20 +970,17 @@ int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
   return IBMLBM_OK;
 }
 
-int ibmlbm_read_timing(ibmlbm_t h, double* collide_ms, int64_t* collide_launches, double* marker_ms) {
+int ibmlbm_read_timing(ibmlbm_t h, double* collide_ms, int64_t* collide_launches,
+                       double* collide_cells, double* marker_ms) {
   if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
-    float ms = 0.f;
-    HIP_TRY(h, hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
-    if (h->ev_kind[k / 2] == 0) { h->acc_collide_ms += ms; h->acc_collide_n++; }
-    else h->acc_marker_ms += ms;
-  }
-  h->ev_used = 0;
+  int rc = fold_events(h);
+  if (rc) return rc;
   if (collide_ms) *collide_ms = h->acc_collide_ms;
   if (collide_launches) *collide_launches = h->acc_collide_n;
+  if (collide_cells) *collide_cells = h->acc_collide_cells;
   if (marker_ms) *marker_ms = h->acc_marker_ms;
-  h->acc_collide_ms = h->acc_marker_ms = 0.0;
+  h->acc_collide_ms = h->acc_marker_ms = h->acc_collide_cells = 0.0;
   h->acc_collide_n = 0;
   return IBMLBM_OK;
 }
@@ -942,7 +990,11 @@ int32_t ibmlbm_bytes_per_cell(ibmlbm_t h) { return h ? 2 * kQ * h->L.es : 0; }
 int ibmlbm_destroy(ibmlbm_t h) {
   if (!h) return IBMLBM_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
+  if (h->aux) (void)hipStreamSynchronize(h->aux);
   for (auto& ev : h->ev) (void)hipEventDestroy(ev);
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   if (e != hipSuccess) return fail(nullptr, IBMLBM_EDEVICE, "stream error at destroy: %s", hipGetErrorString(e));
   return IBMLBM_OK;

@@ -111,7 +111,8 @@ struct MarkerArgs {
 };
 
 // launch wrappers (kernels.hip); all enqueue on `s` and return hipError_t
-hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
+enum CollideMode { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BOX = 2 };
+hipError_t launch_collide(int storage, int mode, bool ibm, bool force, bool check,
                           const CollideArgs& a, hipStream_t s);
 hipError_t launch_ghost(int storage, const Geo& g, const Phys& p, void* buf, hipStream_t s);
 hipError_t launch_init_eq(int storage, const Geo& g, const double* rho, const double* u,

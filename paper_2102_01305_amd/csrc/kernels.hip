@@ -189,7 +189,94 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
 }
 
 // ---------------------------------------------------------------- collide --
-template <class St, bool IBM, bool FORCE, bool CHECK>
+
+// True if (x, y) lies in the node box of foil w.
+__device__ __forceinline__ bool in_box(const FoilBox& b, int x, int y) {
+  return y >= b.y0 && y < b.y0 + b.h && x >= b.x0 && x < b.x0 + b.w;
+}
+
+// One cell update: pull-streaming, moments, optional IBM velocity
+// correction and Guo forcing, BGK relaxation, streaming store of the
+// post-collision values and, at x = 0 / nx-1, the ghost layer of the next
+// state.  Returns the density deviation of the pre-collision state.
+template <class St, bool IBM, bool FORCE>
+__device__ __forceinline__ float collide_cell(const CollideArgs& a, const typename St::T* __restrict__ S,
+                                              typename St::T* __restrict__ D, int x, int y, int z) {
+  using T = typename St::T;
+  const Geo& g = a.g;
+  float f[kQ];
+  pull19<St>(S, g, x, y, z, f);
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    drho += f[i];
+    jx += cxq(i) * f[i];
+    jy += cyq(i) * f[i];
+    jz += czq(i) * f[i];
+  }
+  const float rho = 1.0f + drho;
+  const float inv = 1.0f / rho;
+  float Fx = 0.f, Fy = 0.f, Fz = 0.f;
+  if (FORCE) {
+    Fx = a.p.fb[0]; Fy = a.p.fb[1]; Fz = a.p.fb[2];
+    jx += 0.5f * Fx; jy += 0.5f * Fy; jz += 0.5f * Fz;
+  }
+  float ux = jx * inv, uy = jy * inv, uz = jz * inv;
+  bool forced = FORCE;
+  if (IBM) {
+    // du(x) = sum over foils and the 4 span layers within reach of the
+    // layer images written by the spread kernel (Eq. 15)
+    float dux = 0.f, duy = 0.f, duz = 0.f;
+    bool hit = false;
+    for (int w = 0; w < a.nw; ++w) {
+      const FoilBox& b = a.box[w];
+      if (!in_box(b, x, y)) continue;
+      const int lx = x - b.x0, ly = y - b.y0;
+      hit = true;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        int s = z - 2 + k;
+        s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
+        const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
+        dux += a.wz[k] * v.x;
+        duy += a.wz[k] * v.y;
+        duz += a.wz[k] * v.z;
+      }
+    }
+    if (hit) {
+      ux += dux; uy += duy; uz += duz;                 // Eq. 16
+      Fx += 2.0f * rho * dux;                          // Eq. 11 / Eq. 26
+      Fy += 2.0f * rho * duy;
+      Fz += 2.0f * rho * duz;
+      forced = true;
+    }
+  }
+  const float usq = ux * ux + uy * uy + uz * uz;
+  const float om = a.p.omega;
+  float o[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) o[i] = f[i] - om * (f[i] - feq_dev(i, drho, rho, ux, uy, uz, usq));
+  if (forced) {
+    const float k = a.p.guo_k;
+    const float uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
+      const float cF = cxq(i) * Fx + cyq(i) * Fy + czq(i) * Fz;
+      o[i] += k * wq(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);   // Eq. 8
+    }
+  }
+  T* own = D + rowbase(g, y, z);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) St::stn(own + (long long)i * g.ps + x, o[i]);
+  if (x == 0 || x == g.nx - 1) write_ghosts<St>(D, g, a.p, x, y, z, o);
+  return drho;
+}
+
+// MODE 0: every cell.  MODE 1 (bulk): every cell outside all foil boxes,
+// with no correction to apply.  One row per wave, 64 cells along x per
+// wave, 4 waves per block.
+template <class St, bool IBM, bool FORCE, bool CHECK, int MODE>
 __global__ void __launch_bounds__(kBlockX * kBlockRows)
 k_collide(CollideArgs a) {
   using T = typename St::T;
@@ -202,81 +289,20 @@ k_collide(CollideArgs a) {
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
   const int row = __builtin_amdgcn_readfirstlane(rg * kBlockRows + (int)threadIdx.y);
-  const bool active = x < g.nx && row < g.ny * g.nz;
+  bool active = x < g.nx && row < g.ny * g.nz;
   double dm = 0.0;
   bool bad = false;
   if (active) {
     const int z = __builtin_amdgcn_readfirstlane(row / g.ny);
     const int y = __builtin_amdgcn_readfirstlane(row - z * g.ny);
-    float f[kQ];
-    pull19<St>(S, g, x, y, z, f);
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      drho += f[i];
-      jx += cxq(i) * f[i];
-      jy += cyq(i) * f[i];
-      jz += czq(i) * f[i];
-    }
-    const float rho = 1.0f + drho;
-    const float inv = 1.0f / rho;
-    float Fx = 0.f, Fy = 0.f, Fz = 0.f;
-    if (FORCE) {
-      Fx = a.p.fb[0]; Fy = a.p.fb[1]; Fz = a.p.fb[2];
-      jx += 0.5f * Fx; jy += 0.5f * Fy; jz += 0.5f * Fz;
-    }
-    float ux = jx * inv, uy = jy * inv, uz = jz * inv;
-    bool forced = FORCE;
-    if (IBM) {
-      // du(x) = sum over foils and the 4 span layers within reach of the
-      // layer images written by the spread kernel (Eq. 15)
-      float dux = 0.f, duy = 0.f, duz = 0.f;
-      bool hit = false;
-      for (int w = 0; w < a.nw; ++w) {
-        const FoilBox& b = a.box[w];
-        const int lx = x - b.x0, ly = y - b.y0;
-        if (ly < 0 || ly >= b.h || lx < 0 || lx >= b.w) continue;
-        hit = true;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          int s = z - 2 + k;
-          s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
-          const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
-          dux += a.wz[k] * v.x;
-          duy += a.wz[k] * v.y;
-          duz += a.wz[k] * v.z;
-        }
+    if (MODE == 1)
+      for (int w = 0; w < a.nw; ++w) active = active && !in_box(a.box[w], x, y);
+    if (active) {
+      const float drho = collide_cell<St, IBM && MODE == 0, FORCE>(a, S, D, x, y, z);
+      if (CHECK) {
+        dm = (double)drho;
+        bad = !isfinite(drho);
       }
-      if (hit) {
-        ux += dux; uy += duy; uz += duz;                 // Eq. 16
-        Fx += 2.0f * rho * dux;                          // Eq. 11 / Eq. 26
-        Fy += 2.0f * rho * duy;
-        Fz += 2.0f * rho * duz;
-        forced = true;
-      }
-    }
-    const float usq = ux * ux + uy * uy + uz * uz;
-    const float om = a.p.omega;
-    float o[kQ];
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) o[i] = f[i] - om * (f[i] - feq_dev(i, drho, rho, ux, uy, uz, usq));
-    if (forced) {
-      const float k = a.p.guo_k;
-      const float uF = ux * Fx + uy * Fy + uz * Fz;
-#pragma unroll
-      for (int i = 0; i < kQ; ++i) {
-        const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
-        const float cF = cxq(i) * Fx + cyq(i) * Fy + czq(i) * Fz;
-        o[i] += k * wq(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);   // Eq. 8
-      }
-    }
-    T* own = D + rowbase(g, y, z);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) St::stn(own + (long long)i * g.ps + x, o[i]);
-    if (x == 0 || x == g.nx - 1) write_ghosts<St>(D, g, a.p, x, y, z, o);
-    if (CHECK) {
-      dm = (double)drho;
-      bad = !isfinite(drho);
     }
   }
   if (CHECK) {
@@ -295,34 +321,73 @@ k_collide(CollideArgs a) {
   }
 }
 
-template <class St, bool IBM, bool FORCE, bool CHECK>
+// The cells of the foil boxes (each cell of their union once), with the
+// IBM correction.  Threads run over the flattened (layer, box row, x) cells
+// of each box so that every lane of a wave has a cell.
+template <class St, bool FORCE>
+__global__ void __launch_bounds__(256) k_collide_box(CollideArgs a) {
+  using T = typename St::T;
+  const T* __restrict__ S = static_cast<const T*>(a.src);
+  T* __restrict__ D = static_cast<T*>(a.dst);
+  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int wi = 0;
+  while (wi < a.nw) {
+    const long long n = (long long)a.box[wi].w * a.box[wi].h * a.g.nz;
+    if (c < n) break;
+    c -= n;
+    ++wi;
+  }
+  if (wi >= a.nw) return;
+  const FoilBox& b = a.box[wi];
+  const int lx = (int)(c % b.w);
+  const long long r = c / b.w;
+  const int y = b.y0 + (int)(r % b.h), z = (int)(r / b.h);
+  const int x = b.x0 + lx;
+  for (int k = 0; k < wi; ++k)
+    if (in_box(a.box[k], x, y)) return;
+  collide_cell<St, true, FORCE>(a, S, D, x, y, z);
+}
+
+template <class St, bool IBM, bool FORCE, bool CHECK, int MODE>
 static hipError_t launch_collide_t(const CollideArgs& a, hipStream_t s) {
-  k_collide<St, IBM, FORCE, CHECK><<<a.nblocks, dim3(kBlockX, kBlockRows), 0, s>>>(a);
+  k_collide<St, IBM, FORCE, CHECK, MODE><<<a.nblocks, dim3(kBlockX, kBlockRows), 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <class St>
-static hipError_t launch_collide_s(bool ibm, bool force, bool check, const CollideArgs& a,
+static hipError_t launch_collide_s(int mode, bool ibm, bool force, bool check, const CollideArgs& a,
                                    hipStream_t s) {
+  if (mode == COLLIDE_BOX) {
+    long long cells = 0;
+    for (int w = 0; w < a.nw; ++w) cells += (long long)a.box[w].w * a.box[w].h * a.g.nz;
+    const unsigned nb = (unsigned)((cells + 255) / 256);
+    if (nb == 0) return hipSuccess;
+    if (force) k_collide_box<St, true><<<nb, 256, 0, s>>>(a);
+    else k_collide_box<St, false><<<nb, 256, 0, s>>>(a);
+    return hipGetLastError();
+  }
+  if (mode == COLLIDE_BULK)
+    return force ? launch_collide_t<St, false, true, false, 1>(a, s)
+                 : launch_collide_t<St, false, false, false, 1>(a, s);
   const int key = (ibm ? 4 : 0) | (force ? 2 : 0) | (check ? 1 : 0);
   switch (key) {
-    case 0: return launch_collide_t<St, false, false, false>(a, s);
-    case 1: return launch_collide_t<St, false, false, true>(a, s);
-    case 2: return launch_collide_t<St, false, true, false>(a, s);
-    case 3: return launch_collide_t<St, false, true, true>(a, s);
-    case 4: return launch_collide_t<St, true, false, false>(a, s);
-    case 5: return launch_collide_t<St, true, false, true>(a, s);
-    case 6: return launch_collide_t<St, true, true, false>(a, s);
-    default: return launch_collide_t<St, true, true, true>(a, s);
+    case 0: return launch_collide_t<St, false, false, false, 0>(a, s);
+    case 1: return launch_collide_t<St, false, false, true, 0>(a, s);
+    case 2: return launch_collide_t<St, false, true, false, 0>(a, s);
+    case 3: return launch_collide_t<St, false, true, true, 0>(a, s);
+    case 4: return launch_collide_t<St, true, false, false, 0>(a, s);
+    case 5: return launch_collide_t<St, true, false, true, 0>(a, s);
+    case 6: return launch_collide_t<St, true, true, false, 0>(a, s);
+    default: return launch_collide_t<St, true, true, true, 0>(a, s);
   }
 }
 
-hipError_t launch_collide(int storage, bool ibm, bool force, bool check, const CollideArgs& a,
-                          hipStream_t s) {
+hipError_t launch_collide(int storage, int mode, bool ibm, bool force, bool check,
+                          const CollideArgs& a, hipStream_t s) {
   switch (storage) {
-    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, a, s);
-    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, a, s);
-    default: return launch_collide_s<StBF16>(ibm, force, check, a, s);
+    case ST_F32: return launch_collide_s<StF32>(mode, ibm, force, check, a, s);
+    case ST_F16: return launch_collide_s<StF16>(mode, ibm, force, check, a, s);
+    default: return launch_collide_s<StBF16>(mode, ibm, force, check, a, s);
   }
 }
 

@@ -176,9 +176,12 @@ class Solver:
     def read_timing(self):
         c = C.c_double()
         n = C.c_int64()
+        cells = C.c_double()
         m = C.c_double()
-        L.check(self.lib.ibmlbm_read_timing(self.h, C.byref(c), C.byref(n), C.byref(m)), self.h)
-        return dict(collide_ms=c.value, collide_launches=int(n.value), marker_ms=m.value)
+        L.check(self.lib.ibmlbm_read_timing(self.h, C.byref(c), C.byref(n), C.byref(cells),
+                                            C.byref(m)), self.h)
+        return dict(collide_ms=c.value, collide_launches=int(n.value), collide_cells=cells.value,
+                    marker_ms=m.value)
 
     @property
     def bytes_per_cell(self):
