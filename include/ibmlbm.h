@@ -19,10 +19,7 @@
  *    The library never allocates device memory.  The library owns only the
  *    host-side handle.  Input arrays are copied, never retained.
  *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
- *    void*; NULL = the null stream).  The marker kernels of a step run on
- *    an internal stream that forks from and joins back into the caller's
- *    stream within the step, so the caller's stream orders all the work of
- *    every step.  step() only enqueues; forces(),
+ *    void*; NULL = the null stream).  step() only enqueues; forces(),
  *    fields(), mass() and destroy() synchronise the stream.  A device error
  *    raised by enqueued work is reported by the next synchronising call as
  *    IBMLBM_EDEVICE.
@@ -169,15 +166,12 @@ IBMLBM_API int32_t ibmlbm_marker_count(ibmlbm_t h);
  * if none yet.  Returns EDIVERGED once a check has seen a non-finite value. */
 IBMLBM_API int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass);
 
-/* Kernel timing: with enable = k > 0 the lattice-wide collide-stream launch
- * and the marker kernels of every k-th step are bracketed by HIP events
- * (recorded without a system-scope fence) on the streams they run on;
- * read_timing synchronises, returns the summed milliseconds, count and
- * updated cells of the bracketed collide launches and the summed marker
- * milliseconds, and resets the sums.  enable = 0 stops recording.  On steps
- * with foils the lattice-wide launch covers the cells outside the foils'
- * node boxes (the box cells follow in a small launch once the marker
- * kernels, which run concurrently on an internal stream, are done). */
+/* Kernel timing: with enable = k > 0 the collide-stream launch and the
+ * marker kernels of every k-th step are bracketed by HIP events (recorded
+ * without a system-scope fence) on the handle's stream; read_timing
+ * synchronises, returns the summed milliseconds, count and updated cells of
+ * the bracketed collide launches and the summed marker milliseconds, and
+ * resets the sums.  enable = 0 stops recording. */
 IBMLBM_API int ibmlbm_timing(ibmlbm_t h, int32_t enable);
 IBMLBM_API int ibmlbm_read_timing(ibmlbm_t h, double* collide_ms, int64_t* collide_launches,
                                   double* collide_cells, double* marker_ms);

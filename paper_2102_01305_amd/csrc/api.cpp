@@ -1,7 +1,7 @@
 // Host side of libibmlbm: configuration checks, workspace carving, marker
 // geometry, launch order of the time step, and read-back.  See ibmlbm.h for
 // the contract of every entry point.
-#include "../../include/ibmlbm.h"
+#include "ibmlbm.h"
 
 #include <algorithm>
 #include <cmath>
@@ -29,7 +29,8 @@ struct LatticeLayout {
   int es = 4;        // bytes per stored value
   int px = 0;
   long long ps = 0;      // population stride (elements)
-  size_t total = 0;      // elements of one state buffer
+  size_t total = 0;      // elements of the slabs of one state buffer
+  size_t goff = 0;       // byte offset of the ghost records in a state buffer
   size_t N = 0;
   int nxc = 0, nblocks = 0;
   Region fA, fB, mass_part, diag;
@@ -47,7 +48,7 @@ struct WingGeom {
 constexpr int kPwStride = 14;      // doubles per perimeter record (kernels.hip)
 
 struct MarkerLayout {
-  Region ref, G, Minv, pw, C, X, U, B, rhoB, duB, fpart, hist;
+  Region ref, G, Minv, pw, C, T, X, U, B, rhoB, duB, fpart, hist;
   std::vector<Region> band, corr;
   size_t end = 0;
   int m_total = 0, layers = 0, perims = 0;
@@ -59,8 +60,6 @@ struct MarkerLayout {
 struct ibmlbm_s {
   ibmlbm_config cfg{};
   hipStream_t stream = nullptr;
-  hipStream_t aux = nullptr;        // marker kernels, overlapped with the bulk collide
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   LatticeLayout L;
@@ -156,8 +155,10 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   L.nblocks = L.nxc * ((c->ny * c->nz + kBlockRows - 1) / kBlockRows);
   size_t o = 0;
   auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + bytes); };
-  take(L.fA, L.total * L.es);
-  take(L.fB, L.total * L.es);
+  L.goff = align256(L.total * L.es);
+  const size_t state = L.goff + 2 * (size_t)c->ny * c->nz * 32;
+  take(L.fA, state);
+  take(L.fB, state);
   take(L.mass_part, (size_t)L.nblocks * sizeof(double));
   take(L.diag, 64);
   L.end = o;
@@ -471,12 +472,13 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
   M.minv_step = (int)nMinv;
   M.pw_step = M.perims * kPwStride;
   take(M.C, 3 * m * 8);
+  take(M.T, 3 * m * 8);
   take(M.X, 3 * m * 8);
   take(M.U, 3 * m * 8);
   take(M.B, 3 * m * 8);
   take(M.rhoB, m * 8);
   take(M.duB, 3 * m * 8);
-  take(M.fpart, 4 * (size_t)M.perims * 8);
+  take(M.fpart, 4 * (size_t)M.layers * 8);
   M.band.resize(nw);
   M.corr.resize(nw);
   for (int k = 0; k < nw; ++k) {
@@ -572,16 +574,13 @@ int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, v
   h->geo.nz = cfg->nz;
   h->geo.px = L.px;
   h->geo.ps = L.ps;
+  h->geo.goff = (long long)L.goff;
   h->geo.yper = cfg->bc[2] == IBMLBM_BC_PERIODIC;
   h->geo.zper = cfg->bc[4] == IBMLBM_BC_PERIODIC;
   h->geo.bclo = cfg->bc[0];
   h->geo.bchi = cfg->bc[1];
   fill_phys(h);
-  hipError_t e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
-  // fork/join events order kernels of one device: no system-scope fence
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming | hipEventDisableSystemFence);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming | hipEventDisableSystemFence);
-  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
+  hipError_t e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     int r = fail(nullptr, IBMLBM_EDEVICE, "create failed: %s", hipGetErrorString(e));
@@ -666,7 +665,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
   h->win_t0 = -1;
   if (n_wings == 0) return IBMLBM_OK;
   std::vector<double> ref, G;
-  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, poff = 0;
+  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, loff = 0;
   for (int k = 0; k < n_wings; ++k) {
     const ibmlbm_wing& w = wings[k];
     h->wings[k] = w;
@@ -679,10 +678,10 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     d.minv_off = moff2;
     d.pw_off = pwoff;
     d.c_off = 3 * moff;
+    d.layer_off = loff;
     d.side = geo[k].side;
     d.band = at<float4>(h, M.band[k]);
     d.corr = at<float4>(h, M.corr[k]);
-    d.fpart = at<double>(h, M.fpart) + 4 * poff;
     d.shape = w.alpha_shape;
     d.hinge0[0] = w.hinge[0];
     d.hinge0[1] = w.hinge[1];
@@ -705,7 +704,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     goff += d.ns;
     moff2 += d.np * d.np;
     pwoff += kPwStride * d.np;
-    poff += d.np;
+    loff += d.ns;
   }
   HIP_TRY(h, hipMemcpyAsync(h->ws + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));
   HIP_TRY(h, hipMemcpyAsync(h->ws + M.G.off, G.data(), G.size() * 8, hipMemcpyHostToDevice, h->stream));
@@ -752,11 +751,17 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
     ma.duB = at<double>(h, h->M.duB);
     ma.pw = at<double>(h, h->M.pw);
     ma.C = at<double>(h, h->M.C);
+    ma.T = at<double>(h, h->M.T);
+    ma.fpart = at<double>(h, h->M.fpart);
+    ca.fpart = ma.fpart;
+    ca.hist = at<double>(h, h->M.hist);
+    ca.qS = 0.5 * c.u_ref * c.u_ref * c.area_ref;
+    for (int k = 0; k < h->nw; ++k) {
+      ca.sense[k] = h->wings[k].sense;
+      ca.chord[k] = h->wings[k].chord;
+    }
     ma.pw_step = h->M.pw_step;
     ma.minv_step = h->M.minv_step;
-    ma.hist = at<double>(h, h->M.hist);
-    ma.u_ref = c.u_ref;
-    ma.area_ref = c.area_ref;
     ma.flags = ca.flags;
   }
   for (int k = 0; k < n; ++k) {
@@ -771,7 +776,7 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
       ma.slot = (int)(s - h->win_t0);
       ma.t = (double)s;
       ma.src = cur_state(h);
-      ma.hist_row = s % c.history_steps;
+      ca.hist_row = s % c.history_steps;
       long long cells = 0;
       for (int w = 0; w < h->nw; ++w) {
         node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
@@ -790,45 +795,19 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
     ca.src = cur_state(h);
     ca.dst = next_state(h);
     const bool check = c.check_interval > 0 && ((s + 1) % c.check_interval == 0);
-    if (ibm && !check) {
-      // The marker kernels and then the update of the foil-box cells run on
-      // the auxiliary stream while the caller's stream updates every cell
-      // outside the boxes.  Both read S^n and write disjoint cells of
-      // S^(n+1); the caller's stream joins the auxiliary one before the
-      // next step, and the next step's marker kernels start after that.
-      long long box_cells = 0;
-      for (int w = 0; w < h->nw; ++w) box_cells += (long long)ca.box[w].w * ca.box[w].h * c.nz;
-      HIP_TRY(h, hipEventRecord(h->ev_fork, h->stream));
-      HIP_TRY(h, hipStreamWaitEvent(h->aux, h->ev_fork, 0));
-      int rc = record_event(h, h->aux, 1, true);
+    if (ibm) {
+      int rc = record_event(h, h->stream, 1, true);
       if (rc) return rc;
-      if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->aux));
-      HIP_TRY(h, launch_markers(c.storage, ma, h->aux));
-      rc = record_event(h, h->aux, 1, false);
-      if (rc) return rc;
-      HIP_TRY(h, launch_collide(c.storage, COLLIDE_BOX, true, force, false, ca, h->aux));
-      HIP_TRY(h, hipEventRecord(h->ev_join, h->aux));
-      rc = record_event(h, h->stream, 0, true, (double)L.N - (double)box_cells);
-      if (rc) return rc;
-      HIP_TRY(h, launch_collide(c.storage, COLLIDE_BULK, false, force, false, ca, h->stream));
-      rc = record_event(h, h->stream, 0, false);
-      if (rc) return rc;
-      HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_join, 0));
-    } else {
-      if (ibm) {
-        int rc = record_event(h, h->stream, 1, true);
-        if (rc) return rc;
-        if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
-        HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
-        rc = record_event(h, h->stream, 1, false);
-        if (rc) return rc;
-      }
-      int rc = record_event(h, h->stream, 0, true, (double)L.N);
-      if (rc) return rc;
-      HIP_TRY(h, launch_collide(c.storage, COLLIDE_ALL, ibm, force, check, ca, h->stream));
-      rc = record_event(h, h->stream, 0, false);
+      if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
+      HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
+      rc = record_event(h, h->stream, 1, false);
       if (rc) return rc;
     }
+    int rc = record_event(h, h->stream, 0, true, (double)L.N);
+    if (rc) return rc;
+    HIP_TRY(h, launch_collide(c.storage, ibm, force, check, ca, h->stream));
+    rc = record_event(h, h->stream, 0, false);
+    if (rc) return rc;
     if (check)
       HIP_TRY(h, launch_mass_reduce(ca.mass_part, L.nblocks, (double)L.N,
                                     reinterpret_cast<double*>(h->ws + L.diag.off), s + 1, h->stream));
@@ -990,11 +969,7 @@ int32_t ibmlbm_bytes_per_cell(ibmlbm_t h) { return h ? 2 * kQ * h->L.es : 0; }
 int ibmlbm_destroy(ibmlbm_t h) {
   if (!h) return IBMLBM_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
-  if (h->aux) (void)hipStreamSynchronize(h->aux);
   for (auto& ev : h->ev) (void)hipEventDestroy(ev);
-  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
-  if (h->ev_join) (void)hipEventDestroy(h->ev_join);
-  if (h->aux) (void)hipStreamDestroy(h->aux);
   delete h;
   if (e != hipSuccess) return fail(nullptr, IBMLBM_EDEVICE, "stream error at destroy: %s", hipGetErrorString(e));
   return IBMLBM_OK;

@@ -20,13 +20,14 @@ enum Bc { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
 // Padded distribution layout, row-major slabs: population q of row
-// r = z*ny + y, cell x, lives at element ((r+1)*19 + q)*px + x.  The element
-// before x = 0 is the x = -1 ghost of that (row, population) and element nx
-// the x = nx ghost; px >= nx + 2 and px*elem is a multiple of 128 bytes so
-// every population row starts on a cache line.  The first slab is padding.
+// r = z*ny + y, cell x, lives at element ((r+1)*19 + q)*px + x; px >= nx + 2
+// and px*elem is a multiple of 128 bytes so every population row starts on a
+// cache line.  The first slab is padding.  After the slabs, at byte offset
+// goff, each state keeps its x-face ghost records: 32 bytes per row and side.
 struct Geo {
   int nx, ny, nz, px;
   long long ps;        // population stride within a slab (= px)
+  long long goff;      // byte offset of a state's ghost records from its base
   int yper, zper;      // periodic y / z
   int bclo, bchi;      // kinds of the -x / +x faces
 };
@@ -59,9 +60,15 @@ struct CollideArgs {
   FoilBox box[kMaxWings];
   float wz[4];               // span weights delta(1.5), delta(0.5), delta(0.5), delta(1.5)
   int nxc;                   // 64-wide chunks along x
-  int nblocks;
+  int nblocks;               // row groups of 4 rows x 64 cells
   double* mass_part;         // per-block partial sums (check steps)
   int* flags;                // bit 0: non-finite density seen
+  // force reduction by block 0 on steps with foils
+  const double* fpart;       // [nw][nz][4] layer forces and moments
+  double* hist;              // [H][nw][8]
+  long long hist_row;
+  double qS;                 // 0.5 u_ref^2 area_ref
+  double sense[kMaxWings], chord[kMaxWings];
 };
 
 struct WingDev {
@@ -70,14 +77,14 @@ struct WingDev {
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
   int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
-  int c_off;                 // offset of this foil's intermediate C (np x 3 x ns)
+  int c_off;                 // offset of this foil's intermediates B, T (np x 3 x ns)
+  int layer_off;             // offset of this foil's layers in the force partials
   int shape;
   double hinge0[2], theta0, sense, mean, amp, period, phase, tamp, tang;
   double dA, chord;
   int x0, y0, bw, bh, side;  // this step's node box (see FoilBox)
   float4* band;              // band moments over the box
   float4* corr;              // spread correction over the box
-  double* fpart;             // per perimeter marker: Fx, Fy, Fz, Mz of its span column
 };
 
 struct MarkerArgs {
@@ -98,21 +105,19 @@ struct MarkerArgs {
   long long win_t0;          // first step of the precomputed window
   int slot;                  // this step's slot in the window
   int pw_step, minv_step;    // doubles per slot
-  double* C;
+  double* C;                 // B column-major: [marker p][component][layer]
+  double* T;                 // span-solved B, layer-major: [layer][marker p][component]
+  double* fpart;             // [layer]: Fx, Fy, Fz, Mz of each span layer
   double* X;                 // 3 per marker
   double* U;                 // 3 per marker
   double* B;                 // 3 per marker
   double* rhoB;              // 1 per marker
   double* duB;               // 3 per marker
-  double* hist;              // [H][nw][8]
-  long long hist_row;        // row of this step in the ring
-  double u_ref, area_ref;
   int* flags;                // bit 1: singular perimeter system
 };
 
 // launch wrappers (kernels.hip); all enqueue on `s` and return hipError_t
-enum CollideMode { COLLIDE_ALL = 0, COLLIDE_BULK = 1, COLLIDE_BOX = 2 };
-hipError_t launch_collide(int storage, int mode, bool ibm, bool force, bool check,
+hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
                           const CollideArgs& a, hipStream_t s);
 hipError_t launch_ghost(int storage, const Geo& g, const Phys& p, void* buf, hipStream_t s);
 hipError_t launch_init_eq(int storage, const Geo& g, const double* rho, const double* u,

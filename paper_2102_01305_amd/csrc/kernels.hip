@@ -8,11 +8,11 @@
 //            no-slip matrix and its inverse (Eq. 18), for a window of steps.
 //  band      rho, u* over the node box of each foil (Eqs. 2, 11).
 //  interp    delta interpolation of rho and u* to the markers (Eqs. 14, 17),
-//            B = U_B - I u* (Eq. 19), then the perimeter solve per layer.
-//  span      the span part of the minimum-norm solve (Eq. 19), du_B, and the
-//            force and moment of each span column (Eq. 26).
-//  spread    sum_l du_B D dA over each layer of each foil's box (Eq. 15);
-//            the fixed-order force sum and coefficients of each foil.
+//            B = U_B - I u* (Eq. 19).
+//  span      the span part of the minimum-norm solve (Eq. 19).
+//  layer     the perimeter part of the solve, du_B, the force and moment of
+//            each layer (Eq. 26) and sum_l du_B D dA over the layer (Eq. 15).
+//  collide   (block 0) the fixed-order force sum and coefficients.
 //
 // Distributions are stored as deviations from the lattice weights,
 // f~_i = f_i - w_i, so FP32 (and 16-bit) storage keeps the small velocity
@@ -82,10 +82,32 @@ __device__ __forceinline__ long long rowbase(const Geo& g, int y, int z) {
   return (long long)(z * g.ny + y + 1) * (kQ * g.px);
 }
 
+// Slot of population i among the five that cross an x face (c_x = +1:
+// 1, 7, 9, 11, 13; c_x = -1: 2, 8, 10, 12, 14).
+__host__ __device__ constexpr int xslot(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 0, 0, 0, 0};
+  return t[i];
+}
+
+// Ghost values of a state: what the x = -1 (side 0) and x = nx (side 1)
+// cells hold for the populations that enter the box from there, one
+// 32-byte record per lattice row and side, after the state's slabs.  A block
+// of 4 rows writes one whole 128-byte line per side.
+template <class T>
+__device__ __forceinline__ T* ghost_ptr(T* state, const Geo& g, int side, int y, int z, int i) {
+  constexpr int per = 32 / (int)sizeof(T);
+  T* base = reinterpret_cast<T*>(reinterpret_cast<char*>(state) + g.goff);
+  return base + ((long long)side * g.ny * g.nz + (long long)z * g.ny + y) * per + xslot(i);
+}
+template <class T>
+__device__ __forceinline__ const T* ghost_ptr(const T* state, const Geo& g, int side, int y, int z, int i) {
+  return ghost_ptr(const_cast<T*>(state), g, side, y, z, i);
+}
+
 // Pre-collision distributions of cell (x, y, z): pull f~_i from x - c_i of
 // the post-collision state S.  y/z: periodic wrap or half-way bounce-back
-// (f_i <- S_opp(i) of the cell itself).  x: through the ghost layer, which
-// holds the periodic image, the bounce-back value or the inlet/outlet
+// (f_i <- S_opp(i) of the cell itself).  x: from the ghost records of S,
+// which hold the periodic image, the bounce-back value or the inlet/outlet
 // equilibrium.  All 19 source rows are chosen first, without branches, so
 // the loads issue back to back; when y and z are wave-uniform the row
 // pointers stay in scalar registers.
@@ -110,12 +132,14 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
       wall = wall || (out && !g.zper);
       zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
     }
-    const T* pn = S + (long long)i * g.ps + rowbase(g, yy, zz) - cx;
-    const T* pb = own + (long long)oppq(i) * g.ps;
+    const T* pn = S + (long long)i * g.ps + rowbase(g, yy, zz) - cx + x;
+    if (cx == 1) pn = x == 0 ? ghost_ptr(S, g, 0, yy, zz, i) : pn;
+    if (cx == -1) pn = x == g.nx - 1 ? ghost_ptr(S, g, 1, yy, zz, i) : pn;
+    const T* pb = own + (long long)oppq(i) * g.ps + x;
     src[i] = wall ? pb : pn;
   }
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) f[i] = St::ld(src[i] + x);
+  for (int i = 0; i < kQ; ++i) f[i] = St::ld(src[i]);
 }
 
 // Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
@@ -125,14 +149,13 @@ __device__ __forceinline__ float feq_dev(int i, float drho, float rho, float ux,
   return wq(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
 }
 
-// Ghost layer of the state being written, from the post-collision values
+// Ghost records of the state being written, from the post-collision values
 // `o` of a boundary cell (x == 0 or x == nx-1).  The ghost at (-1, y', z')
 // for population i (c_x = +1) is read only by cell (0, y'+c_y, z'+c_z); the
 // +x ghost likewise for c_x = -1.
 template <class St>
 __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const Phys& p,
                              int x, int y, int z, const float o[kQ]) {
-  const long long rb = rowbase(g, y, z);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -148,12 +171,11 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
     const int kind = side == 0 ? g.bclo : g.bchi;
     const int bcell = side == 0 ? 0 : g.nx - 1; // boundary cell feeding this face
     const int pcell = side == 0 ? g.nx - 1 : 0; // periodic image feeding this face
-    const long long gcol = side == 0 ? -1 : g.nx;
     if (kind == BC_PERIODIC) {
       if (x != pcell) continue;
 #pragma unroll
       for (int i = 0; i < kQ; ++i)
-        if (cxq(i) == dir) St::st(D + (long long)i * g.ps + rb + gcol, o[i]);
+        if (cxq(i) == dir) St::st(ghost_ptr(D, g, side, y, z, i), o[i]);
       continue;
     }
     if (x != bcell) continue;
@@ -167,7 +189,7 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
         else if (yy >= g.ny) { if (g.yper) yy -= g.ny; else skip = true; }
         if (zz < 0) { if (g.zper) zz += g.nz; else skip = true; }
         else if (zz >= g.nz) { if (g.zper) zz -= g.nz; else skip = true; }
-        if (!skip) St::st(D + (long long)i * g.ps + rowbase(g, yy, zz) + gcol, o[oppq(i)]);
+        if (!skip) St::st(ghost_ptr(D, g, side, yy, zz, i), o[oppq(i)]);
       }
       continue;
     }
@@ -184,7 +206,7 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
       if (cxq(i) == dir)
-        St::st(D + (long long)i * g.ps + rb + gcol, feq_dev(i, rg - 1.0f, rg, ux, uy, uz, usq));
+        St::st(ghost_ptr(D, g, side, y, z, i), feq_dev(i, rg - 1.0f, rg, ux, uy, uz, usq));
   }
 }
 
@@ -273,36 +295,66 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   return drho;
 }
 
-// MODE 0: every cell.  MODE 1 (bulk): every cell outside all foil boxes,
-// with no correction to apply.  One row per wave, 64 cells along x per
-// wave, 4 waves per block.
-template <class St, bool IBM, bool FORCE, bool CHECK, int MODE>
+// Block 0 of a collide launch after the marker kernels: per foil, the sum
+// over span layers of the layer forces and moments in a fixed order, the
+// coefficients (Sec. 3.6-3.7: lift is the lateral component, counted outward
+// for a mirrored pair; thrust is -F_x; drag = -thrust) and the history row.
+__device__ void reduce_forces(const CollideArgs& a) {
+  __shared__ double red[4][kBlockX * kBlockRows];
+  const int t = threadIdx.y * kBlockX + threadIdx.x, nt = kBlockX * kBlockRows;
+  for (int w = 0; w < a.nw; ++w) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* fp = a.fpart + 4 * (size_t)w * a.g.nz;
+    for (int l = t; l < a.g.nz; l += nt)
+      for (int k = 0; k < 4; ++k) v[k] += fp[4 * l + k];
+    for (int k = 0; k < 4; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int h = nt / 2; h > 0; h >>= 1) {
+      if (t < h)
+        for (int k = 0; k < 4; ++k) red[k][t] += red[k][t + h];
+      __syncthreads();
+    }
+    if (t == 0) {
+      const double F0 = red[0][0], F1 = red[1][0], F2 = red[2][0], F3 = red[3][0];
+      double* h = a.hist + ((size_t)a.hist_row * a.nw + w) * 8;
+      h[0] = F0;
+      h[1] = F1;
+      h[2] = F2;
+      h[3] = F3;
+      h[4] = -a.sense[w] * F1 / a.qS;
+      h[5] = -F0 / a.qS;
+      h[6] = F0 / a.qS;
+      h[7] = F3 / (a.qS * a.chord[w]);
+    }
+    __syncthreads();
+  }
+}
+
+// Every cell, one row per wave, 64 cells along x per wave, 4 waves per block.
+template <class St, bool IBM, bool FORCE, bool CHECK>
 __global__ void __launch_bounds__(kBlockX * kBlockRows)
 k_collide(CollideArgs a) {
   using T = typename St::T;
   const Geo& g = a.g;
   const T* __restrict__ S = static_cast<const T*>(a.src);
   T* __restrict__ D = static_cast<T*>(a.dst);
+  if (IBM && blockIdx.x == 0) reduce_forces(a);
   const int lb = blockIdx.x;
   const int xc = lb % a.nxc;
   const int rg = lb / a.nxc;
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
   const int row = __builtin_amdgcn_readfirstlane(rg * kBlockRows + (int)threadIdx.y);
-  bool active = x < g.nx && row < g.ny * g.nz;
+  const bool active = x < g.nx && row < g.ny * g.nz;
   double dm = 0.0;
   bool bad = false;
   if (active) {
     const int z = __builtin_amdgcn_readfirstlane(row / g.ny);
     const int y = __builtin_amdgcn_readfirstlane(row - z * g.ny);
-    if (MODE == 1)
-      for (int w = 0; w < a.nw; ++w) active = active && !in_box(a.box[w], x, y);
-    if (active) {
-      const float drho = collide_cell<St, IBM && MODE == 0, FORCE>(a, S, D, x, y, z);
-      if (CHECK) {
-        dm = (double)drho;
-        bad = !isfinite(drho);
-      }
+    const float drho = collide_cell<St, IBM, FORCE>(a, S, D, x, y, z);
+    if (CHECK) {
+      dm = (double)drho;
+      bad = !isfinite(drho);
     }
   }
   if (CHECK) {
@@ -321,73 +373,34 @@ k_collide(CollideArgs a) {
   }
 }
 
-// The cells of the foil boxes (each cell of their union once), with the
-// IBM correction.  Threads run over the flattened (layer, box row, x) cells
-// of each box so that every lane of a wave has a cell.
-template <class St, bool FORCE>
-__global__ void __launch_bounds__(256) k_collide_box(CollideArgs a) {
-  using T = typename St::T;
-  const T* __restrict__ S = static_cast<const T*>(a.src);
-  T* __restrict__ D = static_cast<T*>(a.dst);
-  long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int wi = 0;
-  while (wi < a.nw) {
-    const long long n = (long long)a.box[wi].w * a.box[wi].h * a.g.nz;
-    if (c < n) break;
-    c -= n;
-    ++wi;
-  }
-  if (wi >= a.nw) return;
-  const FoilBox& b = a.box[wi];
-  const int lx = (int)(c % b.w);
-  const long long r = c / b.w;
-  const int y = b.y0 + (int)(r % b.h), z = (int)(r / b.h);
-  const int x = b.x0 + lx;
-  for (int k = 0; k < wi; ++k)
-    if (in_box(a.box[k], x, y)) return;
-  collide_cell<St, true, FORCE>(a, S, D, x, y, z);
-}
-
-template <class St, bool IBM, bool FORCE, bool CHECK, int MODE>
+template <class St, bool IBM, bool FORCE, bool CHECK>
 static hipError_t launch_collide_t(const CollideArgs& a, hipStream_t s) {
-  k_collide<St, IBM, FORCE, CHECK, MODE><<<a.nblocks, dim3(kBlockX, kBlockRows), 0, s>>>(a);
+  k_collide<St, IBM, FORCE, CHECK><<<a.nblocks, dim3(kBlockX, kBlockRows), 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <class St>
-static hipError_t launch_collide_s(int mode, bool ibm, bool force, bool check, const CollideArgs& a,
+static hipError_t launch_collide_s(bool ibm, bool force, bool check, const CollideArgs& a,
                                    hipStream_t s) {
-  if (mode == COLLIDE_BOX) {
-    long long cells = 0;
-    for (int w = 0; w < a.nw; ++w) cells += (long long)a.box[w].w * a.box[w].h * a.g.nz;
-    const unsigned nb = (unsigned)((cells + 255) / 256);
-    if (nb == 0) return hipSuccess;
-    if (force) k_collide_box<St, true><<<nb, 256, 0, s>>>(a);
-    else k_collide_box<St, false><<<nb, 256, 0, s>>>(a);
-    return hipGetLastError();
-  }
-  if (mode == COLLIDE_BULK)
-    return force ? launch_collide_t<St, false, true, false, 1>(a, s)
-                 : launch_collide_t<St, false, false, false, 1>(a, s);
   const int key = (ibm ? 4 : 0) | (force ? 2 : 0) | (check ? 1 : 0);
   switch (key) {
-    case 0: return launch_collide_t<St, false, false, false, 0>(a, s);
-    case 1: return launch_collide_t<St, false, false, true, 0>(a, s);
-    case 2: return launch_collide_t<St, false, true, false, 0>(a, s);
-    case 3: return launch_collide_t<St, false, true, true, 0>(a, s);
-    case 4: return launch_collide_t<St, true, false, false, 0>(a, s);
-    case 5: return launch_collide_t<St, true, false, true, 0>(a, s);
-    case 6: return launch_collide_t<St, true, true, false, 0>(a, s);
-    default: return launch_collide_t<St, true, true, true, 0>(a, s);
+    case 0: return launch_collide_t<St, false, false, false>(a, s);
+    case 1: return launch_collide_t<St, false, false, true>(a, s);
+    case 2: return launch_collide_t<St, false, true, false>(a, s);
+    case 3: return launch_collide_t<St, false, true, true>(a, s);
+    case 4: return launch_collide_t<St, true, false, false>(a, s);
+    case 5: return launch_collide_t<St, true, false, true>(a, s);
+    case 6: return launch_collide_t<St, true, true, false>(a, s);
+    default: return launch_collide_t<St, true, true, true>(a, s);
   }
 }
 
-hipError_t launch_collide(int storage, int mode, bool ibm, bool force, bool check,
-                          const CollideArgs& a, hipStream_t s) {
+hipError_t launch_collide(int storage, bool ibm, bool force, bool check, const CollideArgs& a,
+                          hipStream_t s) {
   switch (storage) {
-    case ST_F32: return launch_collide_s<StF32>(mode, ibm, force, check, a, s);
-    case ST_F16: return launch_collide_s<StF16>(mode, ibm, force, check, a, s);
-    default: return launch_collide_s<StBF16>(mode, ibm, force, check, a, s);
+    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, a, s);
+    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, a, s);
+    default: return launch_collide_s<StBF16>(ibm, force, check, a, s);
   }
 }
 
@@ -690,190 +703,185 @@ __global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
   }
 }
 
-// Blocks that work on span layers take kLayerPair of them at once, one
-// 256-thread half-block per layer; block b covers layers 2 j, 2 j + 1 of a foil.
-constexpr int kLayerPair = 2;
-
-__device__ __forceinline__ int find_pair_block(const MarkerArgs& a, int blk, int& wi) {
+__device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, int& wi) {
   wi = 0;
-  while (wi + 1 < a.nw) {
-    const int pairs = (a.w[wi].ns + kLayerPair - 1) / kLayerPair;
-    if (blk < pairs) break;
-    blk -= pairs;
+  while (wi + 1 < a.nw && blk >= a.w[wi].ns) {
+    blk -= a.w[wi].ns;
     ++wi;
   }
   return blk;
 }
 
-// Block (foil, pair of span layers): for each perimeter marker p, one wave
-// with a lane per node of its 4x4x4 support interpolates rho and u*
-// (Eq. 17) in FP64, B = U_B - I u* (Eq. 19); then C[p] = sum_q
-// M_xy^-1[p][q] B[q] for the layer.  Marker X, U, rho_B and B are kept for
-// the caller.  The perimeter records and the inverse are staged in LDS.
-__global__ void __launch_bounds__(512) k_interp(MarkerArgs a) {
+// Block (foil, span layer s): delta interpolation of rho and u* to the
+// layer's markers (Eq. 17) and B = U_B - I u* (Eq. 19), in FP64.  The span
+// factor of D is applied first: H(x, y) = sum_k wz_k band(x, y, s - 1 + k)
+// over the foil's box, kept in LDS; then one thread per marker sums its
+// 4 x 4 xy nodes.  B is also written column-major (marker, component, layer)
+// for the span solve.
+__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
   extern __shared__ double lds[];
-  __shared__ double Bl[kLayerPair][kMaxPerim * 3];
   int wi;
-  const int pair = find_pair_block(a, blockIdx.x, wi);
+  const int s = find_layer_block(a, blockIdx.x, wi);
   const WingDev& w = a.w[wi];
-  const int n = w.np, ns = w.ns;
-  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
-  const int s = pair * kLayerPair + half;
-  double* P = lds;              // n * kPw
-  double* Mi = lds + n * kPw;   // n * n
+  const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
+  double* P = lds;                 // n * kPw
+  double* H = P + n * kPw;         // cells * 4
   const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
-  const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
   for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int ly = c / w.bw, lx = c - ly * w.bw;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int z = s - 1 + k;
+      z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
+      const float4 v = w.band[((long long)z * w.side + ly) * w.side + lx];
+      h0 += a.wz[k] * (double)v.x;
+      h1 += a.wz[k] * (double)v.y;
+      h2 += a.wz[k] * (double)v.z;
+      h3 += a.wz[k] * (double)v.w;
+    }
+    H[4 * c] = h0;
+    H[4 * c + 1] = h1;
+    H[4 * c + 2] = h2;
+    H[4 * c + 3] = h3;
+  }
   __syncthreads();
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
-  const int wave = tid >> 6, lane = tid & 63;
-  const int ox = lane & 3, oy = (lane >> 2) & 3, oz = lane >> 4;
-  if (s < ns) {
-    int zn = s - 1 + oz;
-    zn = zn < 0 ? zn + a.g.nz : (zn >= a.g.nz ? zn - a.g.nz : zn);
-    const float4* layer = w.band + (long long)zn * w.side * w.side;
-    const double wz = a.wz[oz];
-    // markers p = wave + 4 j, eight at a time: issue the eight band loads
-    // before the first reduction
-    constexpr int kChunk = 8;
-    for (int j0 = wave; j0 < n; j0 += 4 * kChunk) {
-      float4 v[kChunk];
-      double D[kChunk];
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double* r = P + p * kPw;
+    const int bx = (int)r[12] - w.x0, by = (int)r[13] - w.y0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const int p = j0 + 4 * u;
-        if (p < n) {
-          const double* r = P + p * kPw;
-          const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
-          v[u] = layer[ly * w.side + lx];
-          D[u] = r[4 + ox] * r[8 + oy] * wz;
-        }
-      }
+    for (int oy = 0; oy < 4; ++oy) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const int p = j0 + 4 * u;
-        if (p >= n) break;
-        const double* r = P + p * kPw;
-        double s0 = D[u] * (double)v[u].x, s1 = D[u] * (double)v[u].y;
-        double s2 = D[u] * (double)v[u].z, s3 = D[u] * (double)v[u].w;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-          s0 += __shfl_xor(s0, off);
-          s1 += __shfl_xor(s1, off);
-          s2 += __shfl_xor(s2, off);
-          s3 += __shfl_xor(s3, off);
-        }
-        if (lane == 0) {
-          const size_t m = (size_t)w.moff + (size_t)p * ns + s;
-          const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
-          a.X[3 * m] = r[0];
-          a.X[3 * m + 1] = r[1];
-          a.X[3 * m + 2] = s + 0.5;
-          a.U[3 * m] = Ux;
-          a.U[3 * m + 1] = Uy;
-          a.U[3 * m + 2] = 0.0;
-          a.rhoB[m] = s0;
-          const double b0 = Ux - s1, b1 = Uy - s2, b2 = 0.0 - s3;   // Eq. 19: B = U_B - I u*
-          a.B[3 * m] = b0;
-          a.B[3 * m + 1] = b1;
-          a.B[3 * m + 2] = b2;
-          Bl[half][3 * p] = b0;
-          Bl[half][3 * p + 1] = b1;
-          Bl[half][3 * p + 2] = b2;
-        }
+      for (int ox = 0; ox < 4; ++ox) {
+        const double D = r[4 + ox] * r[8 + oy];
+        const double* h = H + 4 * ((by + oy) * w.bw + bx + ox);
+        s0 += D * h[0];
+        s1 += D * h[1];
+        s2 += D * h[2];
+        s3 += D * h[3];
       }
     }
-  }
-  __syncthreads();
-  if (s >= ns) return;
-  for (int e = tid; e < 3 * n; e += 256) {
-    const int p = e / 3, comp = e - 3 * p;
-    double acc0 = 0.0, acc1 = 0.0;
-    int q = 0;
-    for (; q + 1 < n; q += 2) {
-      acc0 += Mi[p * n + q] * Bl[half][3 * q + comp];
-      acc1 += Mi[p * n + q + 1] * Bl[half][3 * (q + 1) + comp];
+    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
+    a.X[3 * m] = r[0];
+    a.X[3 * m + 1] = r[1];
+    a.X[3 * m + 2] = s + 0.5;
+    a.U[3 * m] = Ux;
+    a.U[3 * m + 1] = Uy;
+    a.U[3 * m + 2] = 0.0;
+    a.rhoB[m] = s0;
+    const double b[3] = {Ux - s1, Uy - s2, 0.0 - s3};   // Eq. 19: B = U_B - I u*
+    for (int c = 0; c < 3; ++c) {
+      a.B[3 * m + c] = b[c];
+      a.C[w.c_off + ((size_t)p * 3 + c) * ns + s] = b[c];
     }
-    if (q < n) acc0 += Mi[p * n + q] * Bl[half][3 * q + comp];
-    a.C[w.c_off + ((size_t)p * 3 + comp) * ns + s] = acc0 + acc1;
   }
 }
 
-// Block (foil, perimeter marker p): y = M_z^+ C along the span (circular
-// convolution with the pseudo-inverse row G), du_B = y / dA, and the force
-// and moment of the span column (Eq. 26: f_B = 2 rho_B du_B, body force
-// -f_B dA = -2 rho_B y), reduced in a fixed order.
+// Block (foil, perimeter marker p): the span part of the minimum-norm solve,
+// T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
+// row of the circulant span factor.  Each thread makes four consecutive
+// outputs from a sliding window of G.  T is written layer-major.
 __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   extern __shared__ double lds[];
-  __shared__ double red[4][256];
   int wi = 0, p = blockIdx.x;
   while (wi + 1 < a.nw && p >= a.w[wi].np) {
     p -= a.w[wi].np;
     ++wi;
   }
   const WingDev& w = a.w[wi];
-  const int ns = w.ns;
-  double* G = lds;
-  double* Cc = lds + ns;
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) G[i] = a.G[w.g_off + i];
-  const double* Cg = a.C + w.c_off + (size_t)p * 3 * ns;
-  for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Cc[i] = Cg[i];
+  const int ns = w.ns, n = w.np;
+  double* G = lds;          // 2 * ns: G repeated so that G[d + ns] = G[d]
+  double* Bc = lds + 2 * ns; // 3 * ns
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const double g = a.G[w.g_off + i];
+    G[i] = g;
+    G[i + ns] = g;
+  }
+  const double* Bg = a.C + w.c_off + (size_t)p * 3 * ns;
+  for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Bc[i] = Bg[i];
+  __syncthreads();
+  for (int s0 = 4 * threadIdx.x; s0 < ns; s0 += 4 * blockDim.x) {
+    const int cnt = ns - s0 < 4 ? ns - s0 : 4;
+    double acc[4][3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+    // output s0 + j takes G[(s0 + j - s2) mod ns] = G[s0 + j - s2 + ns]
+    double g0 = G[s0 + ns], g1 = G[(s0 + 1) % ns + ns], g2 = G[(s0 + 2) % ns + ns],
+           g3 = G[(s0 + 3) % ns + ns];
+    for (int s2 = 0; s2 < ns; ++s2) {
+      const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
+      acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
+      acc[1][0] += g1 * b0; acc[1][1] += g1 * b1; acc[1][2] += g1 * b2;
+      acc[2][0] += g2 * b0; acc[2][1] += g2 * b1; acc[2][2] += g2 * b2;
+      acc[3][0] += g3 * b0; acc[3][1] += g3 * b1; acc[3][2] += g3 * b2;
+      // slide: next s2 needs G[s0 + j - s2 - 1 + ns]
+      g3 = g2;
+      g2 = g1;
+      g1 = g0;
+      g0 = G[s0 - s2 - 1 + ns];   // in [s0, s0 + ns - 1]
+    }
+    for (int j = 0; j < cnt; ++j)
+      for (int c = 0; c < 3; ++c)
+        a.T[w.c_off + ((size_t)(s0 + j) * n + p) * 3 + c] = acc[j][c];
+  }
+}
+
+// Block (foil, span layer s): the perimeter part of the solve,
+// y(p) = sum_q M_xy^-1[p][q] T(q, s), du_B = y / dA (Eqs. 18-19); the body
+// force and moment of the layer, -2 rho_B y (Eq. 26), reduced in a fixed
+// order; and the xy image of sum_p du_B D_xy dA over the foil's box (Eq. 15
+// without the span factor, which the collide kernel applies), added by one
+// wave in perimeter order so that the sums are the same on every run.
+__global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[4][256];
+  int wi;
+  const int s = find_layer_block(a, blockIdx.x, wi);
+  const WingDev& w = a.w[wi];
+  const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
+  double* Mi = lds;                                  // n * n
+  double* P = Mi + n * n;                            // n * kPw
+  double* Tl = P + n * kPw;                          // n * 3
+  double* Dv = Tl + 3 * n;                           // n * 3 (du_B)
+  float* img = reinterpret_cast<float*>(Dv + 3 * n); // cells * 3
+  const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  const double* Tg = a.T + w.c_off + (size_t)s * n * 3;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) Tl[e] = Tg[e];
+  for (int i = threadIdx.x; i < 3 * cells; i += blockDim.x) img[i] = 0.f;
   __syncthreads();
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
   double fx = 0.0, fy = 0.0, fz = 0.0, mz = 0.0;
-  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
-    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
-    const double r = a.rhoB[m], Xm = a.X[3 * m], Ym = a.X[3 * m + 1];
-    // y_c(s) = sum_s2 G[(s - s2) mod ns] C_c[s2], in two halves without the
-    // modulo, eight terms at a time into split accumulators
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0, z0 = 0.0, z1 = 0.0, z2 = 0.0;
-    {
-      int s2 = 0;
-      for (; s2 + 1 <= s; s2 += 2) {
-        const double g = G[s - s2], h = G[s - s2 - 1];
-        y0 += g * Cc[s2];
-        y1 += g * Cc[ns + s2];
-        y2 += g * Cc[2 * ns + s2];
-        z0 += h * Cc[s2 + 1];
-        z1 += h * Cc[ns + s2 + 1];
-        z2 += h * Cc[2 * ns + s2 + 1];
-      }
-      for (; s2 <= s; ++s2) {
-        const double g = G[s - s2];
-        y0 += g * Cc[s2];
-        y1 += g * Cc[ns + s2];
-        y2 += g * Cc[2 * ns + s2];
-      }
-      for (; s2 + 1 < ns; s2 += 2) {
-        const double g = G[s - s2 + ns], h = G[s - s2 - 1 + ns];
-        y0 += g * Cc[s2];
-        y1 += g * Cc[ns + s2];
-        y2 += g * Cc[2 * ns + s2];
-        z0 += h * Cc[s2 + 1];
-        z1 += h * Cc[ns + s2 + 1];
-        z2 += h * Cc[2 * ns + s2 + 1];
-      }
-      for (; s2 < ns; ++s2) {
-        const double g = G[s - s2 + ns];
-        y0 += g * Cc[s2];
-        y1 += g * Cc[ns + s2];
-        y2 += g * Cc[2 * ns + s2];
-      }
-      y0 += z0;
-      y1 += z1;
-      y2 += z2;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+    for (int q = 0; q < n; ++q) {
+      const double mv = Mi[p * n + q];
+      y0 += mv * Tl[3 * q];
+      y1 += mv * Tl[3 * q + 1];
+      y2 += mv * Tl[3 * q + 2];
     }
-    a.duB[3 * m] = y0 / w.dA;
-    a.duB[3 * m + 1] = y1 / w.dA;
-    a.duB[3 * m + 2] = y2 / w.dA;
+    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    const double d0 = y0 / w.dA, d1 = y1 / w.dA, d2 = y2 / w.dA;
+    a.duB[3 * m] = d0;
+    a.duB[3 * m + 1] = d1;
+    a.duB[3 * m + 2] = d2;
+    Dv[3 * p] = d0;
+    Dv[3 * p + 1] = d1;
+    Dv[3 * p + 2] = d2;
+    const double r = a.rhoB[m];
     const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // on the body
     fx += bx;
     fy += by;
     fz += bz;
-    mz += (Xm - hx) * by - (Ym - hy) * bx;
+    mz += (P[p * kPw] - hx) * by - (P[p * kPw + 1] - hy) * bx;
   }
   red[0][threadIdx.x] = fx;
   red[1][threadIdx.x] = fy;
@@ -885,81 +893,24 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
       for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
     __syncthreads();
   }
-  if (threadIdx.x < 4) w.fpart[4 * p + threadIdx.x] = red[threadIdx.x][0];
-}
-
-// Block (foil, pair of span layers): the xy image of sum_p du_B D_xy dA over
-// the foil's box (Eq. 15 without the span factor, which the collide kernel
-// applies).  Inputs are staged in LDS; one wave per layer then adds the
-// markers in perimeter order, so the sums are the same on every run.  The
-// first block of each foil also sums the span-column forces in a fixed
-// order and writes the coefficients (Sec. 3.6-3.7): lift is the lateral
-// component, counted outward for a mirrored pair; thrust is -F_x; drag is
-// -thrust.
-__global__ void __launch_bounds__(512) k_spread(MarkerArgs a) {
-  extern __shared__ double lds[];
-  __shared__ double red[4][512];
-  int wi;
-  const int pair = find_pair_block(a, blockIdx.x, wi);
-  const WingDev& w = a.w[wi];
-  const int n = w.np;
-  const int half = threadIdx.x >> 8, tid = threadIdx.x & 255;
-  const int s = pair * kLayerPair + half;
-  const int cells = w.bw * w.bh;
-  double* P = lds;                                        // n * kPw
-  double* Dv = P + n * kPw;                               // 2 * n * 3
-  float* img = reinterpret_cast<float*>(Dv + 6 * n) + half * 3 * cells;
-  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
-  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
-  if (s < w.ns)
-    for (int e = tid; e < 3 * n; e += 256) {
-      const int p = e / 3, comp = e - 3 * p;
-      Dv[half * 3 * n + e] = a.duB[3 * ((size_t)w.moff + (size_t)p * w.ns + s) + comp];
-    }
-  for (int i = tid; i < 3 * cells; i += 256) img[i] = 0.f;
-  __syncthreads();
-  if (s < w.ns && tid < 48) {
-    const int node = tid % 16, comp = tid / 16;
+  if (threadIdx.x < 4) a.fpart[4 * ((size_t)w.layer_off + s) + threadIdx.x] = red[threadIdx.x][0];
+  if (threadIdx.x < 48) {
+    const int node = threadIdx.x % 16, comp = threadIdx.x / 16;
     const int ox = node & 3, oy = node >> 2;
-    const double* D = Dv + half * 3 * n;
     for (int p = 0; p < n; ++p) {
       const double* r = P + p * kPw;
-      const double v = r[4 + ox] * r[8 + oy] * w.dA * D[3 * p + comp];
+      const double v = r[4 + ox] * r[8 + oy] * w.dA * Dv[3 * p + comp];
       const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
       img[3 * (ly * w.bw + lx) + comp] += (float)v;
       __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
-  if (s < w.ns) {
-    float4* out = w.corr + (size_t)s * w.side * w.side;
-    for (int i = tid; i < cells; i += 256) {
-      const int ly = i / w.bw, lx = i - ly * w.bw;
-      out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
-    }
+  float4* out = w.corr + (size_t)s * w.side * w.side;
+  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+    const int ly = i / w.bw, lx = i - ly * w.bw;
+    out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
   }
-  if (pair != 0) return;
-  for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = 0.0;
-  for (int q = threadIdx.x; q < n; q += blockDim.x)
-    for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += w.fpart[4 * q + k];
-  __syncthreads();
-  for (int h = 256; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
-      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  const double qS = 0.5 * a.u_ref * a.u_ref * a.area_ref;
-  double* h = a.hist + ((size_t)a.hist_row * a.nw + wi) * 8;
-  const double F0 = red[0][0], F1 = red[1][0], F2 = red[2][0], F3 = red[3][0];
-  h[0] = F0;
-  h[1] = F1;
-  h[2] = F2;
-  h[3] = F3;
-  h[4] = -w.sense * F1 / qS;
-  h[5] = -F0 / qS;
-  h[6] = F0 / qS;
-  h[7] = F3 / (qS * w.chord);
 }
 
 static hipError_t raise_lds(const void* fn, size_t bytes) {
@@ -978,19 +929,21 @@ hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s) {
 }
 
 hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
-  int maxnp = 0, pairs = 0, perims = 0, maxcells = 0, ns = a.g.nz;
+  int maxnp = 0, layers = 0, perims = 0, maxcells = 0, ns = a.g.nz;
   for (int k = 0; k < a.nw; ++k) {
     maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
-    pairs += (a.w[k].ns + kLayerPair - 1) / kLayerPair;
+    layers += a.w[k].ns;
     perims += a.w[k].np;
     const int c = a.w[k].bw * a.w[k].bh;
     maxcells = c > maxcells ? c : maxcells;
   }
-  const size_t lds_i = ((size_t)maxnp * maxnp + (size_t)kPw * maxnp) * sizeof(double);
-  const size_t lds_s = ((size_t)(kPw + 6) * maxnp) * sizeof(double) +
-                       (size_t)kLayerPair * maxcells * 3 * sizeof(float);
+  const size_t lds_i = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
+  const size_t lds_l = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
+                       (size_t)maxcells * 3 * sizeof(float);
+  const size_t lds_s = 5 * (size_t)ns * sizeof(double);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
-  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_spread), lds_s);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_span), lds_s);
   if (e != hipSuccess) return e;
   const unsigned nb = (unsigned)a.band_blocks;   // 4 box rows per block
   switch (storage) {
@@ -1000,13 +953,13 @@ hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_interp<<<pairs, 512, lds_i, s>>>(a);
+  k_interp<<<layers, 256, lds_i, s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_span<<<perims, 256, 4 * (size_t)ns * sizeof(double), s>>>(a);
+  k_span<<<perims, 256, lds_s, s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_spread<<<pairs, 512, lds_s, s>>>(a);
+  k_layer<<<layers, 256, lds_l, s>>>(a);
   return hipGetLastError();
 }
 
