@@ -788,6 +788,19 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
         cells += (long long)b.w * b.h * c.nz;
       }
       ma.band_cells = (int)cells;
+      // as many partial spread images as fit beside the layer kernel's
+      // other LDS (inverse, records, solution) in 150 KiB
+      {
+        int maxnp = 0, maxcells = 0;
+        for (int w = 0; w < h->nw; ++w) {
+          maxnp = std::max(maxnp, ma.w[w].np);
+          maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
+        }
+        const size_t fixed = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192;
+        const size_t per = (size_t)maxcells * 12;
+        ma.copies = 4;
+        while (ma.copies > 1 && fixed + ma.copies * per > 150 * 1024) --ma.copies;
+      }
       long long box_rows = 0;
       for (int w = 0; w < h->nw; ++w) box_rows += (long long)ma.w[w].bh * c.nz;
       ma.band_blocks = (int)((box_rows + 3) / 4);

@@ -113,6 +113,7 @@ struct MarkerArgs {
   double* B;                 // 3 per marker
   double* rhoB;              // 1 per marker
   double* duB;               // 3 per marker
+  int copies;                // partial spread images per layer block (1..4)
   int* flags;                // bit 1: singular perimeter system
 };
 

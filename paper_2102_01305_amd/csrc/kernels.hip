@@ -785,7 +785,8 @@ __global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
 // Block (foil, perimeter marker p): the span part of the minimum-norm solve,
 // T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
 // row of the circulant span factor.  Each thread makes four consecutive
-// outputs from a sliding window of G.  T is written layer-major.
+// outputs from a sliding window of G over one part of the s2 range; the
+// parts are added in a fixed order.  T is written layer-major.
 __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   extern __shared__ double lds[];
   int wi = 0, p = blockIdx.x;
@@ -795,8 +796,12 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   }
   const WingDev& w = a.w[wi];
   const int ns = w.ns, n = w.np;
-  double* G = lds;          // 2 * ns: G repeated so that G[d + ns] = G[d]
-  double* Bc = lds + 2 * ns; // 3 * ns
+  const int groups = (ns + 3) / 4;                   // threads per part
+  int parts = (int)blockDim.x / groups;
+  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+  double* G = lds;              // 2 * ns: G repeated so that G[d + ns] = G[d]
+  double* Bc = G + 2 * ns;      // 3 * ns
+  double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const double g = a.G[w.g_off + i];
     G[i] = g;
@@ -805,29 +810,39 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   const double* Bg = a.C + w.c_off + (size_t)p * 3 * ns;
   for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Bc[i] = Bg[i];
   __syncthreads();
-  for (int s0 = 4 * threadIdx.x; s0 < ns; s0 += 4 * blockDim.x) {
-    const int cnt = ns - s0 < 4 ? ns - s0 : 4;
-    double acc[4][3];
+  const int part = threadIdx.x / groups, t = threadIdx.x - part * groups;
+  if (part < parts) {
+    const int lo = part * ns / parts, hi = (part + 1) * ns / parts;
+    for (int s0 = 4 * t; s0 < ns; s0 += 4 * groups) {
+      double acc[4][3];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-    // output s0 + j takes G[(s0 + j - s2) mod ns] = G[s0 + j - s2 + ns]
-    double g0 = G[s0 + ns], g1 = G[(s0 + 1) % ns + ns], g2 = G[(s0 + 2) % ns + ns],
-           g3 = G[(s0 + 3) % ns + ns];
-    for (int s2 = 0; s2 < ns; ++s2) {
-      const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
-      acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
-      acc[1][0] += g1 * b0; acc[1][1] += g1 * b1; acc[1][2] += g1 * b2;
-      acc[2][0] += g2 * b0; acc[2][1] += g2 * b1; acc[2][2] += g2 * b2;
-      acc[3][0] += g3 * b0; acc[3][1] += g3 * b1; acc[3][2] += g3 * b2;
-      // slide: next s2 needs G[s0 + j - s2 - 1 + ns]
-      g3 = g2;
-      g2 = g1;
-      g1 = g0;
-      g0 = G[s0 - s2 - 1 + ns];   // in [s0, s0 + ns - 1]
+      for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+      // output s0 + j takes G[(s0 + j - s2) mod ns]
+      double g0 = G[(s0 - lo + ns) % ns], g1 = G[(s0 + 1 - lo + ns) % ns],
+             g2 = G[(s0 + 2 - lo + ns) % ns], g3 = G[(s0 + 3 - lo + ns) % ns];
+      for (int s2 = lo; s2 < hi; ++s2) {
+        const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
+        acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
+        acc[1][0] += g1 * b0; acc[1][1] += g1 * b1; acc[1][2] += g1 * b2;
+        acc[2][0] += g2 * b0; acc[2][1] += g2 * b1; acc[2][2] += g2 * b2;
+        acc[3][0] += g3 * b0; acc[3][1] += g3 * b1; acc[3][2] += g3 * b2;
+        // slide to s2 + 1: output s0 + j then takes the old window value j - 1
+        g3 = g2;
+        g2 = g1;
+        g1 = g0;
+        g0 = G[s0 - s2 - 1 + ns];   // index in [s0, s0 + ns - 1]
+      }
+      const int cnt = ns - s0 < 4 ? ns - s0 : 4;
+      for (int j = 0; j < cnt; ++j)
+        for (int c = 0; c < 3; ++c) Pa[((size_t)part * ns + s0 + j) * 3 + c] = acc[j][c];
     }
-    for (int j = 0; j < cnt; ++j)
-      for (int c = 0; c < 3; ++c)
-        a.T[w.c_off + ((size_t)(s0 + j) * n + p) * 3 + c] = acc[j][c];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * ns; e += blockDim.x) {
+    const int sj = e / 3, c = e - 3 * sj;
+    double v = 0.0;
+    for (int q = 0; q < parts; ++q) v += Pa[((size_t)q * ns + sj) * 3 + c];
+    a.T[w.c_off + ((size_t)sj * n + p) * 3 + c] = v;
   }
 }
 
@@ -835,47 +850,51 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
 // y(p) = sum_q M_xy^-1[p][q] T(q, s), du_B = y / dA (Eqs. 18-19); the body
 // force and moment of the layer, -2 rho_B y (Eq. 26), reduced in a fixed
 // order; and the xy image of sum_p du_B D_xy dA over the foil's box (Eq. 15
-// without the span factor, which the collide kernel applies), added by one
-// wave in perimeter order so that the sums are the same on every run.
+// without the span factor, which the collide kernel applies).  The image is
+// built in `a.copies` partial images, each added by one wave over the
+// markers p = copy (mod copies) in order, then summed copy by copy, so the
+// sums are the same on every run.
 __global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
   extern __shared__ double lds[];
   __shared__ double red[4][256];
   int wi;
   const int s = find_layer_block(a, blockIdx.x, wi);
   const WingDev& w = a.w[wi];
-  const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
+  const int n = w.np, ns = w.ns, cells = w.bw * w.bh, copies = a.copies;
   double* Mi = lds;                                  // n * n
   double* P = Mi + n * n;                            // n * kPw
   double* Tl = P + n * kPw;                          // n * 3
-  double* Dv = Tl + 3 * n;                           // n * 3 (du_B)
-  float* img = reinterpret_cast<float*>(Dv + 3 * n); // cells * 3
+  double* Y = Tl + 3 * n;                            // n * 3
+  float* img = reinterpret_cast<float*>(Y + 3 * n);  // copies * cells * 3
   const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
   const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
   const double* Tg = a.T + w.c_off + (size_t)s * n * 3;
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
   for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
   for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) Tl[e] = Tg[e];
-  for (int i = threadIdx.x; i < 3 * cells; i += blockDim.x) img[i] = 0.f;
+  for (int i = threadIdx.x; i < copies * 3 * cells; i += blockDim.x) img[i] = 0.f;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int p = e / 3, c = e - 3 * p;
+    double y0 = 0.0, y1 = 0.0;
+    int q = 0;
+    for (; q + 1 < n; q += 2) {
+      y0 += Mi[p * n + q] * Tl[3 * q + c];
+      y1 += Mi[p * n + q + 1] * Tl[3 * (q + 1) + c];
+    }
+    if (q < n) y0 += Mi[p * n + q] * Tl[3 * q + c];
+    Y[e] = y0 + y1;
+  }
   __syncthreads();
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
   double fx = 0.0, fy = 0.0, fz = 0.0, mz = 0.0;
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    double y0 = 0.0, y1 = 0.0, y2 = 0.0;
-    for (int q = 0; q < n; ++q) {
-      const double mv = Mi[p * n + q];
-      y0 += mv * Tl[3 * q];
-      y1 += mv * Tl[3 * q + 1];
-      y2 += mv * Tl[3 * q + 2];
-    }
+    const double y0 = Y[3 * p], y1 = Y[3 * p + 1], y2 = Y[3 * p + 2];
     const size_t m = (size_t)w.moff + (size_t)p * ns + s;
-    const double d0 = y0 / w.dA, d1 = y1 / w.dA, d2 = y2 / w.dA;
-    a.duB[3 * m] = d0;
-    a.duB[3 * m + 1] = d1;
-    a.duB[3 * m + 2] = d2;
-    Dv[3 * p] = d0;
-    Dv[3 * p + 1] = d1;
-    Dv[3 * p + 2] = d2;
+    a.duB[3 * m] = y0 / w.dA;
+    a.duB[3 * m + 1] = y1 / w.dA;
+    a.duB[3 * m + 2] = y2 / w.dA;
     const double r = a.rhoB[m];
     const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // on the body
     fx += bx;
@@ -887,6 +906,20 @@ __global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
   red[1][threadIdx.x] = fy;
   red[2][threadIdx.x] = fz;
   red[3][threadIdx.x] = mz;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < copies && lane < 48) {
+    // du_B dA D_xy = y D_xy
+    const int node = lane % 16, comp = lane / 16;
+    const int ox = node & 3, oy = node >> 2;
+    float* im = img + (size_t)wave * 3 * cells;
+    for (int p = wave; p < n; p += copies) {
+      const double* r = P + p * kPw;
+      const double v = r[4 + ox] * r[8 + oy] * Y[3 * p + comp];
+      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+      im[3 * (ly * w.bw + lx) + comp] += (float)v;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h)
@@ -894,22 +927,13 @@ __global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
     __syncthreads();
   }
   if (threadIdx.x < 4) a.fpart[4 * ((size_t)w.layer_off + s) + threadIdx.x] = red[threadIdx.x][0];
-  if (threadIdx.x < 48) {
-    const int node = threadIdx.x % 16, comp = threadIdx.x / 16;
-    const int ox = node & 3, oy = node >> 2;
-    for (int p = 0; p < n; ++p) {
-      const double* r = P + p * kPw;
-      const double v = r[4 + ox] * r[8 + oy] * w.dA * Dv[3 * p + comp];
-      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
-      img[3 * (ly * w.bw + lx) + comp] += (float)v;
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
-  __syncthreads();
   float4* out = w.corr + (size_t)s * w.side * w.side;
   for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+    float v[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < copies; ++k)
+      for (int c = 0; c < 3; ++c) v[c] += img[(size_t)k * 3 * cells + 3 * i + c];
     const int ly = i / w.bw, lx = i - ly * w.bw;
-    out[ly * w.side + lx] = make_float4(img[3 * i], img[3 * i + 1], img[3 * i + 2], 0.f);
+    out[ly * w.side + lx] = make_float4(v[0], v[1], v[2], 0.f);
   }
 }
 
@@ -939,8 +963,11 @@ hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
   }
   const size_t lds_i = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
   const size_t lds_l = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
-                       (size_t)maxcells * 3 * sizeof(float);
-  const size_t lds_s = 5 * (size_t)ns * sizeof(double);
+                       (size_t)a.copies * maxcells * 3 * sizeof(float);
+  const int groups = (ns + 3) / 4;
+  int parts = 256 / groups;
+  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+  const size_t lds_s = (5 + 3 * (size_t)parts) * (size_t)ns * sizeof(double);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_span), lds_s);
