@@ -40,7 +40,60 @@ def workload(name):
     if name == "plate":
         bx, wg, ph = WL.plate_case()
         return "plate_64x32x32", bx, wg, ph
+    if name == "tgv":
+        bx, r0, u0, nu = WL.taylor_green_case(256)
+        return "taylor_green_256", bx, [], dict(kind="taylor_green", re=100.0, rho0=r0, u0=u0)
     raise SystemExit(f"unknown workload {name}")
+
+
+# Sources the collide kernel is compiled from: a traffic figure measured with
+# hardware counters holds only while these are unchanged.
+COLLIDE_SOURCES = ("paper_2102_01305_amd/csrc/collide.hip", "paper_2102_01305_amd/csrc/lattice_dev.h",
+                   "paper_2102_01305_amd/csrc/internal.h")
+
+
+def collide_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in COLLIDE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name, storage):
+    """HBM bytes per collide launch from the counter summary under profiles/
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when there is none for this workload or the collide sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"k_collide_{name}_{storage}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and " = " in line:
+                k, v = line[2:].split(" = ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    if kv.get("collide_source_sha256") != collide_source_hash():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes=1 << 30, reps=5):
+    """A plain device copy of known size, for scaling the HBM byte counters:
+    each launch reads and writes `nbytes`."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": reps}))
 
 
 def initial_velocity(bx, ph, u_inf, seed=0):
@@ -49,7 +102,7 @@ def initial_velocity(bx, ph, u_inf, seed=0):
     return u0
 
 
-def cpu_baseline(bx, wg, ph, u0, steps):
+def cpu_baseline(bx, wg, ph, u0, steps, rho0=None):
     """The FP64 oracle on the host, single-threaded, over `steps` steps of
     the same workload (setup excluded)."""
     from threadpoolctl import threadpool_limits
@@ -57,9 +110,12 @@ def cpu_baseline(bx, wg, ph, u0, steps):
     from oracle import params
     from oracle.sim import Sim
 
-    ob, ow = params.complete_case(bx, wg, ph)
+    if ph["kind"] == "taylor_green":
+        ob, ow = bx, wg
+    else:
+        ob, ow = params.complete_case(bx, wg, ph)
     with threadpool_limits(limits=1):
-        s = Sim(ob, ow, u0=u0)
+        s = Sim(ob, ow, rho0=rho0, u0=u0)
         t0 = time.perf_counter()
         s.run(steps)
         dt = time.perf_counter() - t0
@@ -81,23 +137,33 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--timing-every", type=int, default=8,
                     help="bracket the kernels of one step in this many with HIP events")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
               "has no multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
     import torch
 
     from paper_2102_01305_amd.solver import Solver, complete_case
 
     name, bx, wg, ph = workload(args.workload)
-    gb, gw = complete_case(bx, wg, ph)
-    u0 = initial_velocity(bx, ph, gb["u_in"][0])
+    if ph["kind"] == "taylor_green":
+        gb, gw = bx, wg
+        u0, rho0 = ph["u0"], ph["rho0"]
+    else:
+        gb, gw = complete_case(bx, wg, ph)
+        u0, rho0 = initial_velocity(bx, ph, gb["u_in"][0]), None
     print(f"[bench] {name} storage={args.storage} tau={gb['tau']:.4f} steps={args.steps} "
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
     s = Solver(gb, gw, storage=args.storage, history_steps=max(args.steps + args.warmup, 16))
-    s.init_fields(u=u0)
+    s.init_fields(rho=rho0, u=u0)
     N = bx["nx"] * bx["ny"] * bx["nz"]
 
     s.step(args.warmup)
@@ -114,9 +180,13 @@ def main():
     tim = s.read_timing()
     s.enable_timing(0)
     # sanity: the solve is still finite
-    f = s.forces(s.step_count - 1, 1)
-    if not np.all(np.isfinite(f)):
-        raise SystemExit("non-finite forces after the timed run")
+    if gw:
+        f = s.forces(s.step_count - 1, 1)
+        if not np.all(np.isfinite(f)):
+            raise SystemExit("non-finite forces after the timed run")
+    else:
+        if not np.isfinite(s.mass()[1]):
+            raise SystemExit("non-finite mass after the timed run")
     s.close()
 
     mlups = N * args.steps / dt / 1e6
@@ -125,6 +195,7 @@ def main():
     k6_ms = tim["collide_ms"] / nl if nl else float("nan")
     cells_per_launch = tim["collide_cells"] / nl if nl else float("nan")
     achieved = bpc * cells_per_launch / (k6_ms * 1e-3) / 1e9 if nl else float("nan")
+    traffic = measured_traffic(name, args.storage)
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -142,7 +213,7 @@ def main():
                    "re": ph.get("re"), "j": ph.get("j"), "f": ph.get("f"),
                    "wings": len(wg)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide", "kernel_ms": round(k6_ms, 5),
                      "bytes_per_cell": bpc, "cells_per_launch": cells_per_launch,
                      "timed_launches": tim["collide_launches"],
@@ -151,7 +222,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(bx, wg, ph, u0, args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(bx, wg, ph, u0, args.cpu_steps, rho0)
     print(json.dumps(out), flush=True)
 
 

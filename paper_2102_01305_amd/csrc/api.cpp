@@ -615,7 +615,7 @@ int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const dou
             if (L.es == 4) {
               std::memcpy(&host[idx * 4], &v, 4);
             } else if (h->cfg.storage == IBMLBM_FP16_DEV) {
-              _Float16 hv = (_Float16)v;
+              _Float16 hv = (_Float16)(v * kF16Scale);
               std::memcpy(&host[idx * 2], &hv, 2);
             } else {
               uint32_t u32;
@@ -894,7 +894,7 @@ int ibmlbm_fields(ibmlbm_t h, int32_t which, double* out) {
           } else if (h->cfg.storage == IBMLBM_FP16_DEV) {
             _Float16 hv;
             std::memcpy(&hv, &host[idx * 2], 2);
-            v = (float)hv;
+            v = (float)hv * kF16Unscale;
           } else {
             uint16_t b16;
             std::memcpy(&b16, &host[idx * 2], 2);

@@ -1,0 +1,208 @@
+// Device-side lattice helpers shared by the collide and marker kernels:
+// D3Q19 velocity set and weights, the storage formats, the padded row-major
+// slab layout with its x-face ghost records, the pull gather and the
+// equilibrium of the open faces.
+#pragma once
+
+#include <hip/hip_fp16.h>
+
+#include "internal.h"
+
+namespace ibmk {
+
+// ------------------------------------------------------------------ D3Q19 --
+__host__ __device__ constexpr int cxq(int i) {
+  constexpr int t[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return t[i];
+}
+__host__ __device__ constexpr int cyq(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int czq(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return t[i];
+}
+__host__ __device__ constexpr int oppq(int i) {
+  constexpr int t[kQ] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  return t[i];
+}
+__host__ __device__ constexpr float wq(int i) {
+  return i == 0 ? 1.0f / 3.0f : (i < 7 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+__host__ __device__ constexpr double wqd(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------- storage --
+// ld()/st() take and give f~ itself; ldr()/stnr() the stored value, which is
+// kS f~ (kS = 2^12 for FP16, else 1), for the collide kernel, which works
+// in those units throughout.  stn/stnr are streaming (non-temporal) stores
+// for data the current kernel will not read again.
+struct StF32 {
+  using T = float;
+  static constexpr float kS = 1.0f, kInv = 1.0f;
+  __device__ static float ld(const T* p) { return *p; }
+  __device__ static void st(T* p, float v) { *p = v; }
+  __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(v, p); }
+  __device__ static float ldr(const T* p) { return *p; }
+  __device__ static void stnr(T* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+struct StF16 {
+  using T = __half;
+  static constexpr float kS = kF16Scale, kInv = kF16Unscale;
+  __device__ static float ldr(const T* p) { return __half2float(*p); }
+  __device__ static void stnr(T* p, float v) {
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v)), reinterpret_cast<unsigned short*>(p));
+  }
+  __device__ static float ld(const T* p) { return ldr(p) * kInv; }
+  __device__ static void st(T* p, float v) { *p = __float2half_rn(v * kS); }
+  __device__ static void stn(T* p, float v) { stnr(p, v * kS); }
+};
+struct StBF16 {
+  using T = unsigned short;
+  static constexpr float kS = 1.0f, kInv = 1.0f;
+  // round to nearest even (the gfx950 conversion instruction)
+  __device__ static unsigned short enc(float v) { return __builtin_bit_cast(unsigned short, (__bf16)v); }
+  __device__ static float ld(const T* p) { return __uint_as_float(((unsigned)*p) << 16); }
+  __device__ static void st(T* p, float v) { *p = enc(v); }
+  __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
+  __device__ static float ldr(const T* p) { return ld(p); }
+  __device__ static void stnr(T* p, float v) { stn(p, v); }
+};
+
+// Row-major slabs: the 19 populations of one lattice row are adjacent, so a
+// wave's 19 loads and 19 stores stay within a few DRAM pages.
+__device__ __forceinline__ long long rowbase(const Geo& g, int y, int z) {
+  return (long long)(z * g.ny + y + 1) * (kQ * g.px);
+}
+
+// Slot of population i among the five that cross an x face (c_x = +1:
+// 1, 7, 9, 11, 13; c_x = -1: 2, 8, 10, 12, 14).
+__host__ __device__ constexpr int xslot(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 2, 2, 3, 3, 4, 4, 0, 0, 0, 0};
+  return t[i];
+}
+
+// Ghost values of a state: what the x = -1 (side 0) and x = nx (side 1)
+// cells hold for the populations that enter the box from there, one
+// 32-byte record per lattice row and side, after the state's slabs.  A block
+// of 4 rows writes one whole 128-byte line per side.
+template <class T>
+__device__ __forceinline__ T* ghost_ptr(T* state, const Geo& g, int side, int y, int z, int i) {
+  constexpr int per = 32 / (int)sizeof(T);
+  T* base = reinterpret_cast<T*>(reinterpret_cast<char*>(state) + g.goff);
+  return base + ((long long)side * g.ny * g.nz + (long long)z * g.ny + y) * per + xslot(i);
+}
+template <class T>
+__device__ __forceinline__ const T* ghost_ptr(const T* state, const Geo& g, int side, int y, int z, int i) {
+  return ghost_ptr(const_cast<T*>(state), g, side, y, z, i);
+}
+
+// Pre-collision distributions of cell (x, y, z): pull f~_i from x - c_i of
+// the post-collision state S.  y/z: periodic wrap or half-way bounce-back
+// (f_i <- S_opp(i) of the cell itself).  x: from the ghost records of S,
+// which hold the periodic image, the bounce-back value or the inlet/outlet
+// equilibrium.  All 19 source rows are chosen first, without branches, so
+// the loads issue back to back; when y and z are wave-uniform the row
+// pointers stay in scalar registers.  RAW: values in stored units (ldr).
+template <class St, bool RAW = false>
+__device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, const Geo& g,
+                                       int x, int y, int z, float f[kQ]) {
+  using T = typename St::T;
+  const T* src[kQ];
+  const T* own = S + rowbase(g, y, z);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int cy = cyq(i), cz = czq(i), cx = cxq(i);
+    int yy = y - cy, zz = z - cz;
+    bool wall = false;
+    if (cy != 0) {
+      const bool out = yy < 0 || yy >= g.ny;
+      wall = wall || (out && !g.yper);
+      yy = yy < 0 ? yy + g.ny : (yy >= g.ny ? yy - g.ny : yy);
+    }
+    if (cz != 0) {
+      const bool out = zz < 0 || zz >= g.nz;
+      wall = wall || (out && !g.zper);
+      zz = zz < 0 ? zz + g.nz : (zz >= g.nz ? zz - g.nz : zz);
+    }
+    const T* pn = S + (long long)i * g.ps + rowbase(g, yy, zz) - cx + x;
+    if (cx == 1) pn = x == 0 ? ghost_ptr(S, g, 0, yy, zz, i) : pn;
+    if (cx == -1) pn = x == g.nx - 1 ? ghost_ptr(S, g, 1, yy, zz, i) : pn;
+    const T* pb = own + (long long)oppq(i) * g.ps + x;
+    src[i] = wall ? pb : pn;
+  }
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) f[i] = RAW ? St::ldr(src[i]) : St::ld(src[i]);
+}
+
+// Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
+__device__ __forceinline__ float feq_dev(int i, float drho, float rho, float ux, float uy,
+                                         float uz, float usq) {
+  const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
+  return wq(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+}
+
+// Ghost records of the state being written, from the post-collision values
+// `o` of a boundary cell (x == 0 or x == nx-1).  The ghost at (-1, y', z')
+// for population i (c_x = +1) is read only by cell (0, y'+c_y, z'+c_z); the
+// +x ghost likewise for c_x = -1.
+template <class St>
+__device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const Phys& p,
+                             int x, int y, int z, const float o[kQ]) {
+  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    drho += o[i];
+    jx += cxq(i) * o[i];
+    jy += cyq(i) * o[i];
+    jz += czq(i) * o[i];
+  }
+  const float rho = 1.0f + drho;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int dir = side == 0 ? 1 : -1;        // populations leaving the ghost into the box
+    const int kind = side == 0 ? g.bclo : g.bchi;
+    const int bcell = side == 0 ? 0 : g.nx - 1; // boundary cell feeding this face
+    const int pcell = side == 0 ? g.nx - 1 : 0; // periodic image feeding this face
+    if (kind == BC_PERIODIC) {
+      if (x != pcell) continue;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i)
+        if (cxq(i) == dir) St::st(ghost_ptr(D, g, side, y, z, i), o[i]);
+      continue;
+    }
+    if (x != bcell) continue;
+    if (kind == BC_WALL) {
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        if (cxq(i) != dir) continue;
+        int yy = y - cyq(i), zz = z - czq(i);
+        bool skip = false;
+        if (yy < 0) { if (g.yper) yy += g.ny; else skip = true; }
+        else if (yy >= g.ny) { if (g.yper) yy -= g.ny; else skip = true; }
+        if (zz < 0) { if (g.zper) zz += g.nz; else skip = true; }
+        else if (zz >= g.nz) { if (g.zper) zz -= g.nz; else skip = true; }
+        if (!skip) St::st(ghost_ptr(D, g, side, yy, zz, i), o[oppq(i)]);
+      }
+      continue;
+    }
+    float rg, ux, uy, uz;
+    if (kind == BC_VELOCITY) {
+      rg = rho;
+      ux = p.u_in[0]; uy = p.u_in[1]; uz = p.u_in[2];
+    } else {  // BC_PRESSURE
+      rg = p.rho_out;
+      const float inv = 1.0f / rho;
+      ux = jx * inv; uy = jy * inv; uz = jz * inv;
+    }
+    const float usq = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      if (cxq(i) == dir)
+        St::st(ghost_ptr(D, g, side, y, z, i), feq_dev(i, rg - 1.0f, rg, ux, uy, uz, usq));
+  }
+}
+
+}  // namespace ibmk

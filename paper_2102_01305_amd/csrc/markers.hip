@@ -1,0 +1,478 @@
+// gfx950 marker kernels of the implicit IBM (Sec. 2.2).
+//
+//  factor    marker kinematics (Eqs. 20-23), the perimeter block of the
+//            no-slip matrix and its inverse (Eq. 18), for a window of steps.
+//  band      rho, u* over the node box of each foil (Eqs. 2, 11).
+//  interp    delta interpolation of rho and u* to the markers (Eqs. 14, 17),
+//            B = U_B - I u* (Eq. 19).
+//  span      the span part of the minimum-norm solve (Eq. 19).
+//  layer     the perimeter part of the solve, du_B, the force and moment of
+//            each layer (Eq. 26) and sum_l du_B D dA over the layer (Eq. 15).
+#include "lattice_dev.h"
+
+namespace ibmk {
+
+// ---------------------------------------------------------------- markers --
+//
+// An extruded foil has the same perimeter section on every span layer
+// z = s + 1/2, so D = delta_x delta_y delta_z splits into a perimeter part
+// (per step) and a span part whose node weights are the constants
+// delta(1.5), delta(0.5), delta(0.5), delta(1.5).  The no-slip matrix is then
+// M_xy (x) M_z with M = I I^T, and its minimum-norm solution is
+// (M_xy^-1 (x) M_z^+) B (Eqs. 18-19).
+//
+// Per-step perimeter record (stride kPw doubles): X, Y, rx, ry, wx[4], wy[4],
+// bx, by; rx, ry = R(theta) ref, bx/by = floor(X) - 1 (first support node).
+constexpr int kPw = 14;
+
+// Eq. 14: (1 + cos(pi |r| / 2)) / 4 for |r| <= 2, else 0.
+__device__ __forceinline__ double delta_k(double r) {
+  r = fabs(r);
+  return r <= 2.0 ? 0.25 * (1.0 + cos(0.5 * M_PI * r)) : 0.0;
+}
+
+// Chord angle, its rate, pivot position and velocity at time t
+// (Eqs. 20-21, 23; ABS_SIN takes the forward derivative at the kinks, the
+// kink located from the half-period phase so that every side agrees).
+__device__ void wing_pose(const WingDev& w, double t, double& th, double& thd, double& hx,
+                          double& hy, double& vx, double& vy) {
+  double al = w.mean, ald = 0.0;
+  if (w.shape != 0) {
+    const double om = 2.0 * M_PI / w.period;
+    if (w.shape == 1) {
+      const double arg = om * t + w.phase;
+      al = w.mean + w.amp * sin(arg);
+      ald = w.amp * om * cos(arg);
+    } else {
+      const double psi = t / w.period + w.phase / (2.0 * M_PI);
+      const double h = psi - floor(2.0 * psi) / 2.0;
+      al = w.mean + w.amp * sin(2.0 * M_PI * h);
+      ald = w.amp * om * cos(2.0 * M_PI * h);
+    }
+  }
+  th = w.theta0 + w.sense * al;
+  thd = w.sense * ald;
+  hx = w.hinge0[0];
+  hy = w.hinge0[1];
+  vx = 0.0;
+  vy = 0.0;
+  if (w.tamp != 0.0) {
+    const double om = 2.0 * M_PI / w.period;
+    const double arg = om * t + w.phase;
+    const double cb = cos(w.tang), sb = sin(w.tang);
+    hx += w.tamp * cos(arg) * cb;
+    hy += w.tamp * cos(arg) * sb;
+    vx = -w.tamp * om * sin(arg) * cb;
+    vy = -w.tamp * om * sin(arg) * sb;
+  }
+}
+
+// a(p, q) = sum_j delta(j - X_p) delta(j - X_q) from the two 4-node weight
+// sets (1D factor of Eq. 18).
+__device__ __forceinline__ double a1(const double* wp, int bp, const double* wq, int bq) {
+  const int d = bq - bp;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int kk = k - d;
+    if (kk >= 0 && kk < 4) s += wp[k] * wq[kk];
+  }
+  return s;
+}
+
+// Perimeter positions and weights of foil `wi` at time t, the block
+// M_xy[p][q] = a(X_p, X_q) a(Y_p, Y_q) and its inverse by in-place
+// Gauss-Jordan (symmetric positive definite: no pivoting), FP64 in LDS.
+// These depend on the prescribed kinematics only, so they are computed for a
+// window of future steps at once, one block per (step, foil).
+__global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
+  extern __shared__ double lds[];
+  const int slot = blockIdx.x / a.nw, wi = blockIdx.x - slot * a.nw;
+  const WingDev& w = a.w[wi];
+  const int n = w.np;
+  double* M = lds;              // n * n
+  double* P = lds + n * n;      // n * kPw
+  double* colk = P + n * kPw;   // n
+  double th, thd, hx, hy, vx, vy;
+  wing_pose(w, (double)(a.win_t0 + slot), th, thd, hx, hy, vx, vy);
+  const double c = cos(th), sn = sin(th);
+  double* Pg = a.pw + (size_t)slot * a.pw_step + w.pw_off;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double px = a.ref[w.ref_off + 2 * p], py = a.ref[w.ref_off + 2 * p + 1];
+    const double rx = c * px - sn * py, ry = sn * px + c * py;
+    const double X = hx + rx, Y = hy + ry;
+    double* r = P + p * kPw;
+    r[0] = X;
+    r[1] = Y;
+    r[2] = rx;
+    r[3] = ry;
+    const double fx = floor(X) - 1.0, fy = floor(Y) - 1.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      r[4 + k] = delta_k(fx + k - X);
+      r[8 + k] = delta_k(fy + k - Y);
+    }
+    r[12] = fx;
+    r[13] = fy;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) Pg[e] = P[e];
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int p = e / n, q = e - p * n;
+    const double* rp = P + p * kPw;
+    const double* rq = P + q * kPw;
+    M[e] = a1(rp + 4, (int)rp[12], rq + 4, (int)rq[12]) * a1(rp + 8, (int)rp[13], rq + 8, (int)rq[13]);
+  }
+  __syncthreads();
+  __shared__ int singular;
+  if (threadIdx.x == 0) singular = 0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = M[k * n + k];
+    if (!(piv > 1e-300)) {
+      if (threadIdx.x == 0) singular = 1;
+      break;
+    }
+    const double ip = 1.0 / piv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = M[i * n + k];
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += blockDim.x) M[k * n + j] = (j == k ? 1.0 : M[k * n + j]) * ip;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e - i * n;
+      if (i == k) continue;
+      const double base = (j == k) ? 0.0 : M[e];
+      M[e] = base - colk[i] * M[k * n + j];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (singular && threadIdx.x == 0) atomicOr(a.flags, 2);
+  double* out = a.Minv + (size_t)slot * a.minv_step + w.minv_off;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) out[e] = M[e];
+}
+
+// rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
+// pre-collision state at every node of every foil's box, on every layer.
+// One wave per box row (y, z), lanes along x, so rows are wave-uniform.
+template <class St>
+__global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
+  using T = typename St::T;
+  int R = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int lane = threadIdx.x & 63;
+  int wi = 0;
+  while (wi < a.nw) {
+    const int rows = a.w[wi].bh * a.g.nz;
+    if (R < rows) break;
+    R -= rows;
+    ++wi;
+  }
+  if (wi >= a.nw) return;
+  const WingDev& w = a.w[wi];
+  const int ly = R % w.bh, z = R / w.bh;
+  float4* out = w.band + ((long long)z * w.side + ly) * w.side;
+  for (int lx = lane; lx < w.bw; lx += 64) {
+    float f[kQ];
+    pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
+    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      drho += f[i];
+      jx += cxq(i) * f[i];
+      jy += cyq(i) * f[i];
+      jz += czq(i) * f[i];
+    }
+    const float rho = 1.0f + drho;
+    out[lx] = make_float4(rho, (jx + 0.5f * a.p.fb[0]) / rho, (jy + 0.5f * a.p.fb[1]) / rho,
+                          (jz + 0.5f * a.p.fb[2]) / rho);
+  }
+}
+
+__device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, int& wi) {
+  wi = 0;
+  while (wi + 1 < a.nw && blk >= a.w[wi].ns) {
+    blk -= a.w[wi].ns;
+    ++wi;
+  }
+  return blk;
+}
+
+// Block (foil, span layer s): delta interpolation of rho and u* to the
+// layer's markers (Eq. 17) and B = U_B - I u* (Eq. 19), in FP64.  The span
+// factor of D is applied first: H(x, y) = sum_k wz_k band(x, y, s - 1 + k)
+// over the foil's box, kept in LDS; then one thread per marker sums its
+// 4 x 4 xy nodes.  B is also written column-major (marker, component, layer)
+// for the span solve.
+__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
+  extern __shared__ double lds[];
+  int wi;
+  const int s = find_layer_block(a, blockIdx.x, wi);
+  const WingDev& w = a.w[wi];
+  const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
+  double* P = lds;                 // n * kPw
+  double* H = P + n * kPw;         // cells * 4
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int ly = c / w.bw, lx = c - ly * w.bw;
+    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int z = s - 1 + k;
+      z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
+      const float4 v = w.band[((long long)z * w.side + ly) * w.side + lx];
+      h0 += a.wz[k] * (double)v.x;
+      h1 += a.wz[k] * (double)v.y;
+      h2 += a.wz[k] * (double)v.z;
+      h3 += a.wz[k] * (double)v.w;
+    }
+    H[4 * c] = h0;
+    H[4 * c + 1] = h1;
+    H[4 * c + 2] = h2;
+    H[4 * c + 3] = h3;
+  }
+  __syncthreads();
+  double th, thd, hx, hy, vx, vy;
+  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double* r = P + p * kPw;
+    const int bx = (int)r[12] - w.x0, by = (int)r[13] - w.y0;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) {
+#pragma unroll
+      for (int ox = 0; ox < 4; ++ox) {
+        const double D = r[4 + ox] * r[8 + oy];
+        const double* h = H + 4 * ((by + oy) * w.bw + bx + ox);
+        s0 += D * h[0];
+        s1 += D * h[1];
+        s2 += D * h[2];
+        s3 += D * h[3];
+      }
+    }
+    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
+    a.X[3 * m] = r[0];
+    a.X[3 * m + 1] = r[1];
+    a.X[3 * m + 2] = s + 0.5;
+    a.U[3 * m] = Ux;
+    a.U[3 * m + 1] = Uy;
+    a.U[3 * m + 2] = 0.0;
+    a.rhoB[m] = s0;
+    const double b[3] = {Ux - s1, Uy - s2, 0.0 - s3};   // Eq. 19: B = U_B - I u*
+    for (int c = 0; c < 3; ++c) {
+      a.B[3 * m + c] = b[c];
+      a.C[w.c_off + ((size_t)p * 3 + c) * ns + s] = b[c];
+    }
+  }
+}
+
+// Block (foil, perimeter marker p): the span part of the minimum-norm solve,
+// T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
+// row of the circulant span factor.  Each thread makes four consecutive
+// outputs from a sliding window of G over one part of the s2 range; the
+// parts are added in a fixed order.  T is written layer-major.
+__global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
+  extern __shared__ double lds[];
+  int wi = 0, p = blockIdx.x;
+  while (wi + 1 < a.nw && p >= a.w[wi].np) {
+    p -= a.w[wi].np;
+    ++wi;
+  }
+  const WingDev& w = a.w[wi];
+  const int ns = w.ns, n = w.np;
+  const int groups = (ns + 3) / 4;                   // threads per part
+  int parts = (int)blockDim.x / groups;
+  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+  double* G = lds;              // 2 * ns: G repeated so that G[d + ns] = G[d]
+  double* Bc = G + 2 * ns;      // 3 * ns
+  double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const double g = a.G[w.g_off + i];
+    G[i] = g;
+    G[i + ns] = g;
+  }
+  const double* Bg = a.C + w.c_off + (size_t)p * 3 * ns;
+  for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Bc[i] = Bg[i];
+  __syncthreads();
+  const int part = threadIdx.x / groups, t = threadIdx.x - part * groups;
+  if (part < parts) {
+    const int lo = part * ns / parts, hi = (part + 1) * ns / parts;
+    for (int s0 = 4 * t; s0 < ns; s0 += 4 * groups) {
+      double acc[4][3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+      // output s0 + j takes G[(s0 + j - s2) mod ns]
+      double g0 = G[(s0 - lo + ns) % ns], g1 = G[(s0 + 1 - lo + ns) % ns],
+             g2 = G[(s0 + 2 - lo + ns) % ns], g3 = G[(s0 + 3 - lo + ns) % ns];
+      for (int s2 = lo; s2 < hi; ++s2) {
+        const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
+        acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
+        acc[1][0] += g1 * b0; acc[1][1] += g1 * b1; acc[1][2] += g1 * b2;
+        acc[2][0] += g2 * b0; acc[2][1] += g2 * b1; acc[2][2] += g2 * b2;
+        acc[3][0] += g3 * b0; acc[3][1] += g3 * b1; acc[3][2] += g3 * b2;
+        // slide to s2 + 1: output s0 + j then takes the old window value j - 1
+        g3 = g2;
+        g2 = g1;
+        g1 = g0;
+        g0 = G[s0 - s2 - 1 + ns];   // index in [s0, s0 + ns - 1]
+      }
+      const int cnt = ns - s0 < 4 ? ns - s0 : 4;
+      for (int j = 0; j < cnt; ++j)
+        for (int c = 0; c < 3; ++c) Pa[((size_t)part * ns + s0 + j) * 3 + c] = acc[j][c];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * ns; e += blockDim.x) {
+    const int sj = e / 3, c = e - 3 * sj;
+    double v = 0.0;
+    for (int q = 0; q < parts; ++q) v += Pa[((size_t)q * ns + sj) * 3 + c];
+    a.T[w.c_off + ((size_t)sj * n + p) * 3 + c] = v;
+  }
+}
+
+// Block (foil, span layer s): the perimeter part of the solve,
+// y(p) = sum_q M_xy^-1[p][q] T(q, s), du_B = y / dA (Eqs. 18-19); the body
+// force and moment of the layer, -2 rho_B y (Eq. 26), reduced in a fixed
+// order; and the xy image of sum_p du_B D_xy dA over the foil's box (Eq. 15
+// without the span factor, which the collide kernel applies).  The image is
+// built in `a.copies` partial images, each added by one wave over the
+// markers p = copy (mod copies) in order, then summed copy by copy, so the
+// sums are the same on every run.
+__global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double red[4][256];
+  int wi;
+  const int s = find_layer_block(a, blockIdx.x, wi);
+  const WingDev& w = a.w[wi];
+  const int n = w.np, ns = w.ns, cells = w.bw * w.bh, copies = a.copies;
+  double* Mi = lds;                                  // n * n
+  double* P = Mi + n * n;                            // n * kPw
+  double* Tl = P + n * kPw;                          // n * 3
+  double* Y = Tl + 3 * n;                            // n * 3
+  float* img = reinterpret_cast<float*>(Y + 3 * n);  // copies * cells * 3
+  const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
+  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
+  const double* Tg = a.T + w.c_off + (size_t)s * n * 3;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
+  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) Tl[e] = Tg[e];
+  for (int i = threadIdx.x; i < copies * 3 * cells; i += blockDim.x) img[i] = 0.f;
+  __syncthreads();
+  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
+    const int p = e / 3, c = e - 3 * p;
+    double y0 = 0.0, y1 = 0.0;
+    int q = 0;
+    for (; q + 1 < n; q += 2) {
+      y0 += Mi[p * n + q] * Tl[3 * q + c];
+      y1 += Mi[p * n + q + 1] * Tl[3 * (q + 1) + c];
+    }
+    if (q < n) y0 += Mi[p * n + q] * Tl[3 * q + c];
+    Y[e] = y0 + y1;
+  }
+  __syncthreads();
+  double th, thd, hx, hy, vx, vy;
+  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  double fx = 0.0, fy = 0.0, fz = 0.0, mz = 0.0;
+  for (int p = threadIdx.x; p < n; p += blockDim.x) {
+    const double y0 = Y[3 * p], y1 = Y[3 * p + 1], y2 = Y[3 * p + 2];
+    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    a.duB[3 * m] = y0 / w.dA;
+    a.duB[3 * m + 1] = y1 / w.dA;
+    a.duB[3 * m + 2] = y2 / w.dA;
+    const double r = a.rhoB[m];
+    const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // on the body
+    fx += bx;
+    fy += by;
+    fz += bz;
+    mz += (P[p * kPw] - hx) * by - (P[p * kPw + 1] - hy) * bx;
+  }
+  red[0][threadIdx.x] = fx;
+  red[1][threadIdx.x] = fy;
+  red[2][threadIdx.x] = fz;
+  red[3][threadIdx.x] = mz;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (wave < copies && lane < 48) {
+    // du_B dA D_xy = y D_xy
+    const int node = lane % 16, comp = lane / 16;
+    const int ox = node & 3, oy = node >> 2;
+    float* im = img + (size_t)wave * 3 * cells;
+    for (int p = wave; p < n; p += copies) {
+      const double* r = P + p * kPw;
+      const double v = r[4 + ox] * r[8 + oy] * Y[3 * p + comp];
+      const int lx = (int)r[12] + ox - w.x0, ly = (int)r[13] + oy - w.y0;
+      im[3 * (ly * w.bw + lx) + comp] += (float)v;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int k = 0; k < 4; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) a.fpart[4 * ((size_t)w.layer_off + s) + threadIdx.x] = red[threadIdx.x][0];
+  float4* out = w.corr + (size_t)s * w.side * w.side;
+  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+    float v[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < copies; ++k)
+      for (int c = 0; c < 3; ++c) v[c] += img[(size_t)k * 3 * cells + 3 * i + c];
+    const int ly = i / w.bw, lx = i - ly * w.bw;
+    out[ly * w.side + lx] = make_float4(v[0], v[1], v[2], 0.f);
+  }
+}
+
+static hipError_t raise_lds(const void* fn, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s) {
+  int maxnp = 0;
+  for (int k = 0; k < a.nw; ++k) maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+  const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double);
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_factor), lds);
+  if (e != hipSuccess) return e;
+  k_factor<<<(unsigned)(count * a.nw), 256, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
+  int maxnp = 0, layers = 0, perims = 0, maxcells = 0, ns = a.g.nz;
+  for (int k = 0; k < a.nw; ++k) {
+    maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+    layers += a.w[k].ns;
+    perims += a.w[k].np;
+    const int c = a.w[k].bw * a.w[k].bh;
+    maxcells = c > maxcells ? c : maxcells;
+  }
+  const size_t lds_i = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
+  const size_t lds_l = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
+                       (size_t)a.copies * maxcells * 3 * sizeof(float);
+  const int groups = (ns + 3) / 4;
+  int parts = 256 / groups;
+  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+  const size_t lds_s = (5 + 3 * (size_t)parts) * (size_t)ns * sizeof(double);
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_span), lds_s);
+  if (e != hipSuccess) return e;
+  const unsigned nb = (unsigned)a.band_blocks;   // 4 box rows per block
+  switch (storage) {
+    case ST_F32: k_band<StF32><<<nb, 256, 0, s>>>(a); break;
+    case ST_F16: k_band<StF16><<<nb, 256, 0, s>>>(a); break;
+    default: k_band<StBF16><<<nb, 256, 0, s>>>(a); break;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_interp<<<layers, 256, lds_i, s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_span<<<perims, 256, lds_s, s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_layer<<<layers, 256, lds_l, s>>>(a);
+  return hipGetLastError();
+}
+
+}  // namespace ibmk

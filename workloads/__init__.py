@@ -137,6 +137,26 @@ def taylor_green_velocity(n, u0):
     return u
 
 
+def taylor_green_density(n, u0):
+    """Density of the 3D Taylor-Green initial pressure field on an n^3 box:
+    p - p0 = (u0^2 / 16) (cos 2kx + cos 2ky)(cos 2kz + 2) with rho0 = 1 and
+    rho = 1 + 3 (p - p0) (lattice sound speed squared 1/3).  (z, y, x) order."""
+    k = 2.0 * math.pi / n
+    x = np.arange(n, dtype=np.float64)
+    zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+    p = (u0 * u0 / 16.0) * (np.cos(2 * k * xx) + np.cos(2 * k * yy)) * (np.cos(2 * k * zz) + 2.0)
+    return 1.0 + 3.0 * p
+
+
+def taylor_green_case(n=256, re=100.0, u0=0.05):
+    """Fully periodic n^3 box for the Taylor-Green vortex at Re = u0 / (k nu),
+    k = 2 pi / n.  Returns (box, rho0, u0 field, nu)."""
+    k = 2.0 * math.pi / n
+    nu = u0 / (k * re)
+    bx = box(n, n, n, [PERIODIC] * 6, 3.0 * nu + 0.5)
+    return bx, taylor_green_density(n, u0), taylor_green_velocity(n, u0), nu
+
+
 SERVE_DOMAINS = ((64, 64, 64), (96, 80, 80), (128, 96, 96), (160, 128, 128))
 
 
