@@ -126,6 +126,49 @@ def cpu_baseline(bx, wg, ph, u0, steps, rho0=None):
                        f"{dt:.1f} s")
 
 
+def serve_bench(budget_bytes, steps, log=None):
+    """The seeded 64-request sweep (Re x J x f x domain) served twice: all
+    arriving at once (capacity), then with Poisson arrivals at 0.8 of that
+    capacity.  Returns the summaries."""
+    import torch
+
+    from paper_2102_01305_amd.serve import SweepRequest, SweepServer, summarize
+    from paper_2102_01305_amd.solver import complete_case
+
+    def requests(rate):
+        out = []
+        for q in WL.serve_requests(n=64, seed=0, arrival_seed=1, rate=rate, steps=steps):
+            bx, wg, ph = WL.clap_fling_case(nx=q["nx"], ny=q["ny"], nz=q["nz"], chord=q["chord"],
+                                            re=q["re"], j=q["j"], f=q["f"])
+            gb, gw = complete_case(bx, wg, ph)
+
+            def u0(q=q, ui=gb["u_in"][0]):
+                u = WL.velocity_noise((q["nz"], q["ny"], q["nx"]), 1000 + q["id"])
+                u[0] += ui
+                return u
+
+            out.append(SweepRequest(rid=q["id"], box=gb, wings=gw, steps=q["steps"],
+                                    arrival=q["arrival"], u0=u0))
+        return out
+
+    res = {}
+    srv = SweepServer(hbm_budget=budget_bytes, chunk=50)
+    burst = summarize(srv.run(requests(None)))
+    torch.cuda.synchronize()
+    burst["max_batch"] = max(srv.batch_sizes)
+    burst["peak_bytes"] = srv.peak_bytes
+    res["burst"] = burst
+    cap = burst["completed"] / burst["span_s"]
+    srv = SweepServer(hbm_budget=budget_bytes, chunk=50)
+    pois = summarize(srv.run(requests(0.8 * cap)))
+    torch.cuda.synchronize()
+    pois["rate_per_s"] = 0.8 * cap
+    pois["max_batch"] = max(srv.batch_sizes)
+    pois["peak_bytes"] = srv.peak_bytes
+    res["poisson"] = pois
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +182,10 @@ def main():
                     help="bracket the kernels of one step in this many with HIP events")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served sweep")
+    ap.add_argument("--serve-budget-gib", type=float, default=4.0,
+                    help="HBM budget of the served sweep (admission limit)")
+    ap.add_argument("--serve-steps", type=int, default=1000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -220,6 +267,15 @@ def main():
                      "marker_ms_per_step": round(tim["marker_ms"] / max(tim["collide_launches"], 1), 5)},
         "hbm_frac_whole_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
     }
+    if not args.no_serve:
+        print("[bench] served sweep: 64 requests", file=sys.stderr, flush=True)
+        sv = serve_bench(int(args.serve_budget_gib * 2**30), args.serve_steps)
+        out["serving"] = {
+            "requests": 64, "steps_per_request": args.serve_steps,
+            "hbm_budget_gib": args.serve_budget_gib, "storage": "fp32",
+            "burst": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["burst"].items()},
+            "poisson": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["poisson"].items()},
+        }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(bx, wg, ph, u0, args.cpu_steps, rho0)

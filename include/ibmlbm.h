@@ -17,7 +17,9 @@
  *  - Device memory is owned by the caller: one workspace of at least
  *    ibmlbm_workspace_bytes() bytes, 256-byte aligned, handed to create().
  *    The library never allocates device memory.  The library owns only the
- *    host-side handle.  Input arrays are copied, never retained.
+ *    host-side handle and, per handle, a small pinned host buffer (about
+ *    150 KB) through which it uploads the launch arguments of 64 steps at a
+ *    time.  Input arrays are copied, never retained.
  *  - Work is enqueued on the caller's HIP stream (hipStream_t passed as
  *    void*; NULL = the null stream).  step() only enqueues; forces(),
  *    fields(), mass() and destroy() synchronise the stream.  A device error
@@ -142,6 +144,26 @@ IBMLBM_API int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_w
  * t = step, interpolation, the no-slip solve A X = B (Eq. 19, minimum-norm
  * solution), spreading, Guo-forced collision and force integration. */
 IBMLBM_API int ibmlbm_step(ibmlbm_t h, int32_t n);
+
+/* Enqueue n time steps of each of n_handles solves (1..64 distinct,
+ * initialised handles bound to one stream), in lock step: each stage of a
+ * step is one grouped launch over all handles that use the same kernel
+ * (same storage, with or without foils, body force, check step), so many
+ * small solves share the device the way one large solve does.  This is how
+ * the parametric sweep of Sec. 3.3-3.5 (Re, J and f varied) is served.
+ * Every solve runs the same kernels with the same arguments as under
+ * ibmlbm_step, so its results do not depend on the other solves of the
+ * batch.  Timing events (ibmlbm_timing) bracket single-handle steps
+ * only.  EINVAL for a bad handle list or mixed streams; ESTATE if a handle
+ * is not initialised. */
+IBMLBM_API int ibmlbm_step_batch(ibmlbm_t* hs, int32_t n_handles, int32_t n);
+
+/* Move the handle to another HIP stream: waits for the work enqueued on
+ * its current stream, then enqueues everything after on hip_stream.  A
+ * server prepares a new solve (create, set_kinematics, init_fields, which
+ * synchronise their stream) on a side stream while other solves keep
+ * running, then moves it to the stream of its batch (ibmlbm_step_batch). */
+IBMLBM_API int ibmlbm_set_stream(ibmlbm_t h, void* hip_stream);
 
 /* Number of steps taken since init_fields (plus step0). */
 IBMLBM_API int64_t ibmlbm_step_count(ibmlbm_t h);

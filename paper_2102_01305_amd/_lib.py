@@ -54,6 +54,8 @@ SIGNATURES = [
     ("ibmlbm_init_fields", C.c_int, [Handle, _dp, _dp, _dp, C.c_int64]),
     ("ibmlbm_set_kinematics", C.c_int, [Handle, C.c_int32, C.POINTER(Wing)]),
     ("ibmlbm_step", C.c_int, [Handle, C.c_int32]),
+    ("ibmlbm_step_batch", C.c_int, [C.POINTER(Handle), C.c_int32, C.c_int32]),
+    ("ibmlbm_set_stream", C.c_int, [Handle, C.c_void_p]),
     ("ibmlbm_step_count", C.c_int64, [Handle]),
     ("ibmlbm_forces", C.c_int, [Handle, C.c_int64, C.c_int64, _dp]),
     ("ibmlbm_fields", C.c_int, [Handle, C.c_int32, _dp]),

@@ -33,9 +33,13 @@ struct LatticeLayout {
   size_t goff = 0;       // byte offset of the ghost records in a state buffer
   size_t N = 0;
   int nxc = 0, nblocks = 0;
-  Region fA, fB, mass_part, diag;
+  Region fA, fB, mass_part, diag, argtab;
   size_t end = 0;
 };
+
+// Launch arguments of a window of kFactorWindow steps, on the device: the
+// collide arguments of every slot, then the marker arguments of every slot.
+constexpr size_t kArgSlotBytes = sizeof(CollideArgs) + sizeof(MarkerArgs);
 
 struct WingGeom {
   int np = 0;
@@ -75,7 +79,12 @@ struct ibmlbm_s {
   std::vector<WingGeom> geom;
   MarkerLayout M;
   bool markers_valid = false;       // marker outputs of a completed step exist
-  long long win_t0 = -1;            // window of precomputed perimeter factors
+  long long win_t0 = -1;            // window of precomputed factors and launch arguments
+  std::vector<CollideArgs> wca;     // host copies of the window's arguments
+  std::vector<MarkerArgs> wma;
+  void* pin = nullptr;              // pinned staging of the window upload
+  hipEvent_t pin_ev = nullptr;      // completes when the last upload has been read
+  bool pin_pending = false;
   // timing
   bool timing = false;
   int timing_every = 1;             // bracket one step in this many
@@ -161,6 +170,7 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   take(L.fB, state);
   take(L.mass_part, (size_t)L.nblocks * sizeof(double));
   take(L.diag, 64);
+  take(L.argtab, (size_t)kFactorWindow * kArgSlotBytes);
   L.end = o;
   return L;
 }
@@ -198,24 +208,29 @@ struct Arc {
   double a, b;
   std::vector<double> gx, gw;
   int panels = 512;
-  Arc(double a_, double b_) : a(a_), b(b_) { gauss_legendre(16, gx, gw); }
+  std::vector<double> cum;   // arc length at the start of each panel
+  Arc(double a_, double b_) : a(a_), b(b_) {
+    gauss_legendre(16, gx, gw);
+    const double h = 2.0 * M_PI / panels;
+    cum.assign(panels + 1, 0.0);
+    for (int k = 0; k < panels; ++k) cum[k + 1] = cum[k] + piece(k * h, (k + 1) * h);
+  }
   double speed(double t) const { return std::hypot(a * std::sin(t), b * std::cos(t)); }
-  // arc length from 0 to phi (phi in [0, 2 pi]) by composite Gauss-Legendre
+  // Gauss-Legendre integral of the speed over [lo, hi]
+  double piece(double lo, double hi) const {
+    const double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
+    double acc = 0.0;
+    for (size_t j = 0; j < gx.size(); ++j) acc += gw[j] * speed(c + r * gx[j]);
+    return r * acc;
+  }
+  // arc length from 0 to phi (phi in [0, 2 pi]) by composite Gauss-Legendre:
+  // whole panels from the table, then the part of the last panel
   double length(double phi) const {
     const double h = 2.0 * M_PI / panels;
-    double s = 0.0;
     int full = (int)std::floor(phi / h);
-    if (full > panels) full = panels;
-    for (int k = 0; k <= full; ++k) {
-      const double lo = k * h;
-      const double hi = std::min(phi, (k + 1) * h);
-      if (hi <= lo) break;
-      const double c = 0.5 * (lo + hi), r = 0.5 * (hi - lo);
-      double acc = 0.0;
-      for (size_t j = 0; j < gx.size(); ++j) acc += gw[j] * speed(c + r * gx[j]);
-      s += r * acc;
-    }
-    return s;
+    if (full >= panels) return cum[panels];
+    if (full < 0) full = 0;
+    return cum[full] + (phi > full * h ? piece(full * h, phi) : 0.0);
   }
 };
 
@@ -331,11 +346,27 @@ void node_box(const ibmlbm_wing& w, const WingGeom& g, double t, const ibmlbm_co
 // Smallest Cholesky pivot of the perimeter block relative to its largest
 // diagonal entry; <= 0 means not positive definite.
 double perimeter_conditioning(const std::vector<double>& xy, int n, const ibmlbm_config& c) {
+  (void)c;  // the supports of one foil never wrap a periodic axis (checked)
   std::vector<double> M((size_t)n * n);
-  const bool px = c.bc[0] == IBMLBM_BC_PERIODIC, py = c.bc[2] == IBMLBM_BC_PERIODIC;
+  // support nodes floor(X) - 1 .. floor(X) + 2 and their kernel weights, per axis
+  std::vector<int> f0(2 * n);
+  std::vector<double> wt(8 * n);
   for (int p = 0; p < n; ++p)
-    for (int q = 0; q < n; ++q)
-      M[(size_t)p * n + q] = a1_h(xy[2 * p], xy[2 * q], c.nx, px) * a1_h(xy[2 * p + 1], xy[2 * q + 1], c.ny, py);
+    for (int d = 0; d < 2; ++d) {
+      const double X = xy[2 * p + d];
+      f0[2 * p + d] = (int)std::floor(X) - 1;
+      for (int k = 0; k < 4; ++k) wt[8 * p + 4 * d + k] = delta_h(f0[2 * p + d] + k - X);
+    }
+  auto a1 = [&](int p, int q, int d) {
+    const int lo = std::max(f0[2 * p + d], f0[2 * q + d]);
+    const int hi = std::min(f0[2 * p + d], f0[2 * q + d]) + 3;
+    double s = 0.0;
+    for (int j = lo; j <= hi; ++j)
+      s += wt[8 * p + 4 * d + (j - f0[2 * p + d])] * wt[8 * q + 4 * d + (j - f0[2 * q + d])];
+    return s;
+  };
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) M[(size_t)p * n + q] = a1(p, q, 0) * a1(p, q, 1);
   double dmax = 0.0;
   for (int p = 0; p < n; ++p) dmax = std::max(dmax, M[(size_t)p * n + p]);
   double pmin = 1e300;
@@ -537,6 +568,217 @@ int record_event(ibmlbm_t h, hipStream_t st, int kind, bool start, double cells 
   return IBMLBM_OK;
 }
 
+// Arguments of step s whose current state is A if cur_A: the parts that
+// never change for this handle, then the step's own (state buffers, time,
+// window slot, force-history row, node boxes and the grids they imply).
+void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs& ma) {
+  const LatticeLayout& L = h->L;
+  const ibmlbm_config& c = h->cfg;
+  ca = CollideArgs{};
+  ma = MarkerArgs{};
+  ca.g = h->geo;
+  ca.p = h->phys;
+  ca.nw = h->nw;
+  ca.nxc = L.nxc;
+  {
+    const float e = (float)delta_h(1.5), d = (float)delta_h(0.5);
+    ca.wz[0] = e; ca.wz[1] = d; ca.wz[2] = d; ca.wz[3] = e;
+    ma.wz[0] = delta_h(1.5); ma.wz[1] = delta_h(0.5); ma.wz[2] = delta_h(0.5); ma.wz[3] = delta_h(1.5);
+  }
+  ca.nblocks = L.nblocks;
+  ca.mass_part = at<double>(h, L.mass_part);
+  ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
+  void* A = h->ws + L.fA.off;
+  void* B = h->ws + L.fB.off;
+  ca.src = cur_A ? A : B;
+  ca.dst = cur_A ? B : A;
+  if (h->nw == 0) return;
+  ma.g = h->geo;
+  ma.p = h->phys;
+  ma.nw = h->nw;
+  ma.m_total = h->M.m_total;
+  for (int k = 0; k < h->nw; ++k) ma.w[k] = h->wd[k];
+  ma.ref = at<double>(h, h->M.ref);
+  ma.G = at<double>(h, h->M.G);
+  ma.Minv = at<double>(h, h->M.Minv);
+  ma.X = at<double>(h, h->M.X);
+  ma.U = at<double>(h, h->M.U);
+  ma.B = at<double>(h, h->M.B);
+  ma.rhoB = at<double>(h, h->M.rhoB);
+  ma.duB = at<double>(h, h->M.duB);
+  ma.pw = at<double>(h, h->M.pw);
+  ma.C = at<double>(h, h->M.C);
+  ma.T = at<double>(h, h->M.T);
+  ma.fpart = at<double>(h, h->M.fpart);
+  ca.fpart = ma.fpart;
+  ca.hist = at<double>(h, h->M.hist);
+  ca.qS = 0.5 * c.u_ref * c.u_ref * c.area_ref;
+  for (int k = 0; k < h->nw; ++k) {
+    ca.sense[k] = h->wings[k].sense;
+    ca.chord[k] = h->wings[k].chord;
+  }
+  ma.pw_step = h->M.pw_step;
+  ma.minv_step = h->M.minv_step;
+  ma.flags = ca.flags;
+  ma.win_t0 = h->win_t0;
+  ma.slot = (int)(s - h->win_t0);
+  ma.t = (double)s;
+  ma.src = ca.src;
+  ca.hist_row = s % c.history_steps;
+  long long cells = 0, box_rows = 0;
+  int maxnp = 0, maxcells = 0;
+  for (int w = 0; w < h->nw; ++w) {
+    node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
+    FoilBox& b = ca.box[w];
+    b.x0 = ma.w[w].x0; b.y0 = ma.w[w].y0; b.w = ma.w[w].bw; b.h = ma.w[w].bh;
+    b.side = ma.w[w].side;
+    b.band = ma.w[w].band;
+    b.corr = ma.w[w].corr;
+    cells += (long long)b.w * b.h * c.nz;
+    box_rows += (long long)ma.w[w].bh * c.nz;
+    maxnp = std::max(maxnp, ma.w[w].np);
+    maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
+  }
+  ma.band_cells = (int)cells;
+  ma.band_blocks = (int)((box_rows + 3) / 4);
+  // as many partial spread images as fit beside the layer kernel's other
+  // LDS (inverse, records, solution) in 150 KiB
+  const size_t fixed = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192;
+  const size_t per = (size_t)maxcells * 12;
+  ma.copies = 4;
+  while (ma.copies > 1 && fixed + ma.copies * per > 150 * 1024) --ma.copies;
+}
+
+const void* dev_ca(ibmlbm_t h, int slot) {
+  return h->ws + h->L.argtab.off + (size_t)slot * sizeof(CollideArgs);
+}
+const void* dev_ma(ibmlbm_t h, int slot) {
+  return h->ws + h->L.argtab.off + (size_t)kFactorWindow * sizeof(CollideArgs) +
+         (size_t)slot * sizeof(MarkerArgs);
+}
+
+// Start a window at step s0: the arguments of its kFactorWindow steps are
+// made on the host and uploaded in one copy, enqueued on the handle's
+// stream ahead of the window's launches.
+int fill_window(ibmlbm_t h, long long s0) {
+  h->win_t0 = s0;
+  h->wca.resize(kFactorWindow);
+  h->wma.resize(kFactorWindow);
+  for (int k = 0; k < kFactorWindow; ++k)
+    step_args(h, s0 + k, h->cur_is_A == ((k & 1) == 0), h->wca[k], h->wma[k]);
+  if (h->pin_pending) HIP_TRY(h, hipEventSynchronize(h->pin_ev));
+  char* pin = static_cast<char*>(h->pin);
+  std::memcpy(pin, h->wca.data(), (size_t)kFactorWindow * sizeof(CollideArgs));
+  std::memcpy(pin + (size_t)kFactorWindow * sizeof(CollideArgs), h->wma.data(),
+              (size_t)kFactorWindow * sizeof(MarkerArgs));
+  HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.argtab.off, pin, h->L.argtab.bytes, hipMemcpyHostToDevice,
+                            h->stream));
+  HIP_TRY(h, hipEventRecord(h->pin_ev, h->stream));
+  h->pin_pending = true;
+  return IBMLBM_OK;
+}
+
+bool has_force(const ibmlbm_config& c) {
+  return c.body_force[0] != 0.0 || c.body_force[1] != 0.0 || c.body_force[2] != 0.0;
+}
+
+// `steps` time steps of every handle in hs (one stream).  Each stage of a
+// step is one grouped launch over the handles that share its kernel
+// instantiation, so small solves fill the device together and each solve
+// runs the same code as alone.
+int run_steps(ibmlbm_t* hs, int n, int steps) {
+  hipStream_t st = hs[0]->stream;
+  const bool timed = n == 1;
+  std::vector<const MarkerArgs*> mh;
+  std::vector<const CollideArgs*> chh;
+  std::vector<const void*> dv;
+  for (int k = 0; k < steps; ++k) {
+    // windows that start at this step; their factor launch
+    mh.clear();
+    dv.clear();
+    for (int j = 0; j < n; ++j) {
+      ibmlbm_t h = hs[j];
+      const long long s = h->step;
+      if (h->win_t0 < 0 || s < h->win_t0 || s >= h->win_t0 + kFactorWindow) {
+        int rc = fill_window(h, s);
+        if (rc) return rc;
+        if (h->nw > 0) {
+          mh.push_back(&h->wma[0]);
+          dv.push_back(dev_ma(h, 0));
+        }
+      }
+    }
+    bool any_ibm = false;
+    for (int j = 0; j < n; ++j) any_ibm = any_ibm || hs[j]->nw > 0;
+    if (timed && any_ibm) {
+      int rc = record_event(hs[0], st, 1, true);
+      if (rc) return rc;
+    }
+    if (!mh.empty()) {
+      hipError_t e = launch_factor(mh.data(), dv.data(), (int)mh.size(), kFactorWindow, st);
+      if (e != hipSuccess) return fail(hs[0], IBMLBM_EDEVICE, "factor launch: %s", hipGetErrorString(e));
+    }
+    // marker kernels, grouped by storage
+    for (int sto = 0; sto < 3; ++sto) {
+      mh.clear();
+      dv.clear();
+      for (int j = 0; j < n; ++j) {
+        ibmlbm_t h = hs[j];
+        if (h->nw == 0 || h->cfg.storage != sto) continue;
+        const int slot = (int)(h->step - h->win_t0);
+        mh.push_back(&h->wma[slot]);
+        dv.push_back(dev_ma(h, slot));
+      }
+      if (mh.empty()) continue;
+      hipError_t e = launch_markers(sto, mh.data(), dv.data(), (int)mh.size(), st);
+      if (e != hipSuccess) return fail(hs[0], IBMLBM_EDEVICE, "marker launch: %s", hipGetErrorString(e));
+    }
+    if (timed && any_ibm) {
+      int rc = record_event(hs[0], st, 1, false);
+      if (rc) return rc;
+    }
+    // collide, grouped by (storage, foils, body force, check step)
+    if (timed) {
+      int rc = record_event(hs[0], st, 0, true, (double)hs[0]->L.N);
+      if (rc) return rc;
+    }
+    for (int key = 0; key < 24; ++key) {
+      const int sto = key >> 3;
+      const bool ibm = key & 4, force = key & 2, check = key & 1;
+      chh.clear();
+      dv.clear();
+      for (int j = 0; j < n; ++j) {
+        ibmlbm_t h = hs[j];
+        const ibmlbm_config& c = h->cfg;
+        const bool ck = c.check_interval > 0 && ((h->step + 1) % c.check_interval == 0);
+        if (c.storage != sto || (h->nw > 0) != ibm || has_force(c) != force || ck != check) continue;
+        const int slot = (int)(h->step - h->win_t0);
+        chh.push_back(&h->wca[slot]);
+        dv.push_back(dev_ca(h, slot));
+      }
+      if (chh.empty()) continue;
+      hipError_t e = launch_collide(sto, ibm, force, check, chh.data(), dv.data(), (int)chh.size(), st);
+      if (e != hipSuccess) return fail(hs[0], IBMLBM_EDEVICE, "collide launch: %s", hipGetErrorString(e));
+    }
+    if (timed) {
+      int rc = record_event(hs[0], st, 0, false);
+      if (rc) return rc;
+    }
+    for (int j = 0; j < n; ++j) {
+      ibmlbm_t h = hs[j];
+      const ibmlbm_config& c = h->cfg;
+      const long long s = h->step;
+      if (c.check_interval > 0 && ((s + 1) % c.check_interval == 0))
+        HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks, (double)h->L.N,
+                                      reinterpret_cast<double*>(h->ws + h->L.diag.off), s + 1, st));
+      h->cur_is_A = !h->cur_is_A;
+      h->step = s + 1;
+      if (h->nw > 0) h->markers_valid = true;
+    }
+  }
+  return IBMLBM_OK;
+}
+
 }  // namespace
 
 // ================================================================== C ABI ==
@@ -582,6 +824,8 @@ int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, v
   fill_phys(h);
   hipError_t e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess) e = hipHostMalloc(&h->pin, L.argtab.bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     int r = fail(nullptr, IBMLBM_EDEVICE, "create failed: %s", hipGetErrorString(e));
     ibmlbm_destroy(h);
@@ -717,118 +961,22 @@ int ibmlbm_step(ibmlbm_t h, int32_t n) {
   if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
   if (!h->initialized) return fail(h, IBMLBM_ESTATE, "init_fields must be called before step");
   if (n < 0) return fail(h, IBMLBM_EINVAL, "negative step count");
-  const LatticeLayout& L = h->L;
-  const ibmlbm_config& c = h->cfg;
-  const bool force = c.body_force[0] != 0.0 || c.body_force[1] != 0.0 || c.body_force[2] != 0.0;
-  const bool ibm = h->nw > 0;
-  CollideArgs ca{};
-  MarkerArgs ma{};
-  ca.g = h->geo;
-  ca.p = h->phys;
-  ca.nw = h->nw;
-  ca.nxc = L.nxc;
-  {
-    const float e = (float)delta_h(1.5), d = (float)delta_h(0.5);
-    ca.wz[0] = e; ca.wz[1] = d; ca.wz[2] = d; ca.wz[3] = e;
-    ma.wz[0] = delta_h(1.5); ma.wz[1] = delta_h(0.5); ma.wz[2] = delta_h(0.5); ma.wz[3] = delta_h(1.5);
+  return run_steps(&h, 1, n);
+}
+
+int ibmlbm_step_batch(ibmlbm_t* hs, int32_t n_handles, int32_t n) {
+  if (!hs || n_handles < 1 || n_handles > kMaxGroup)
+    return fail(nullptr, IBMLBM_EINVAL, "step_batch takes 1..%d handles", kMaxGroup);
+  if (n < 0) return fail(nullptr, IBMLBM_EINVAL, "negative step count");
+  for (int j = 0; j < n_handles; ++j) {
+    if (!hs[j]) return fail(nullptr, IBMLBM_EINVAL, "null handle %d", j);
+    if (!hs[j]->initialized) return fail(hs[j], IBMLBM_ESTATE, "handle %d: init_fields must be called before step", j);
+    if (hs[j]->stream != hs[0]->stream)
+      return fail(nullptr, IBMLBM_EINVAL, "handles of one batch must share one stream");
+    for (int k = 0; k < j; ++k)
+      if (hs[k] == hs[j]) return fail(nullptr, IBMLBM_EINVAL, "handle %d appears twice", j);
   }
-  ca.nblocks = L.nblocks;
-  ca.mass_part = at<double>(h, L.mass_part);
-  ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
-  if (ibm) {
-    ma.g = h->geo;
-    ma.p = h->phys;
-    ma.nw = h->nw;
-    ma.m_total = h->M.m_total;
-    for (int k = 0; k < h->nw; ++k) ma.w[k] = h->wd[k];
-    ma.ref = at<double>(h, h->M.ref);
-    ma.G = at<double>(h, h->M.G);
-    ma.Minv = at<double>(h, h->M.Minv);
-    ma.X = at<double>(h, h->M.X);
-    ma.U = at<double>(h, h->M.U);
-    ma.B = at<double>(h, h->M.B);
-    ma.rhoB = at<double>(h, h->M.rhoB);
-    ma.duB = at<double>(h, h->M.duB);
-    ma.pw = at<double>(h, h->M.pw);
-    ma.C = at<double>(h, h->M.C);
-    ma.T = at<double>(h, h->M.T);
-    ma.fpart = at<double>(h, h->M.fpart);
-    ca.fpart = ma.fpart;
-    ca.hist = at<double>(h, h->M.hist);
-    ca.qS = 0.5 * c.u_ref * c.u_ref * c.area_ref;
-    for (int k = 0; k < h->nw; ++k) {
-      ca.sense[k] = h->wings[k].sense;
-      ca.chord[k] = h->wings[k].chord;
-    }
-    ma.pw_step = h->M.pw_step;
-    ma.minv_step = h->M.minv_step;
-    ma.flags = ca.flags;
-  }
-  for (int k = 0; k < n; ++k) {
-    const long long s = h->step;
-    bool need_factor = false;
-    if (ibm) {
-      if (h->win_t0 < 0 || s < h->win_t0 || s >= h->win_t0 + kFactorWindow) {
-        h->win_t0 = s;
-        need_factor = true;
-      }
-      ma.win_t0 = h->win_t0;
-      ma.slot = (int)(s - h->win_t0);
-      ma.t = (double)s;
-      ma.src = cur_state(h);
-      ca.hist_row = s % c.history_steps;
-      long long cells = 0;
-      for (int w = 0; w < h->nw; ++w) {
-        node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
-        FoilBox& b = ca.box[w];
-        b.x0 = ma.w[w].x0; b.y0 = ma.w[w].y0; b.w = ma.w[w].bw; b.h = ma.w[w].bh;
-        b.side = ma.w[w].side;
-        b.band = ma.w[w].band;
-        b.corr = ma.w[w].corr;
-        cells += (long long)b.w * b.h * c.nz;
-      }
-      ma.band_cells = (int)cells;
-      // as many partial spread images as fit beside the layer kernel's
-      // other LDS (inverse, records, solution) in 150 KiB
-      {
-        int maxnp = 0, maxcells = 0;
-        for (int w = 0; w < h->nw; ++w) {
-          maxnp = std::max(maxnp, ma.w[w].np);
-          maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
-        }
-        const size_t fixed = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192;
-        const size_t per = (size_t)maxcells * 12;
-        ma.copies = 4;
-        while (ma.copies > 1 && fixed + ma.copies * per > 150 * 1024) --ma.copies;
-      }
-      long long box_rows = 0;
-      for (int w = 0; w < h->nw; ++w) box_rows += (long long)ma.w[w].bh * c.nz;
-      ma.band_blocks = (int)((box_rows + 3) / 4);
-    }
-    ca.src = cur_state(h);
-    ca.dst = next_state(h);
-    const bool check = c.check_interval > 0 && ((s + 1) % c.check_interval == 0);
-    if (ibm) {
-      int rc = record_event(h, h->stream, 1, true);
-      if (rc) return rc;
-      if (need_factor) HIP_TRY(h, launch_factor(ma, kFactorWindow, h->stream));
-      HIP_TRY(h, launch_markers(c.storage, ma, h->stream));
-      rc = record_event(h, h->stream, 1, false);
-      if (rc) return rc;
-    }
-    int rc = record_event(h, h->stream, 0, true, (double)L.N);
-    if (rc) return rc;
-    HIP_TRY(h, launch_collide(c.storage, ibm, force, check, ca, h->stream));
-    rc = record_event(h, h->stream, 0, false);
-    if (rc) return rc;
-    if (check)
-      HIP_TRY(h, launch_mass_reduce(ca.mass_part, L.nblocks, (double)L.N,
-                                    reinterpret_cast<double*>(h->ws + L.diag.off), s + 1, h->stream));
-    h->cur_is_A = !h->cur_is_A;
-    h->step = s + 1;
-    if (ibm) h->markers_valid = true;
-  }
-  return IBMLBM_OK;
+  return run_steps(hs, n_handles, n);
 }
 
 int64_t ibmlbm_step_count(ibmlbm_t h) { return h ? h->step : -1; }
@@ -847,9 +995,12 @@ int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out) {
   HIP_TRY(h, hipMemcpy(&flags, h->ws + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
   const size_t row = (size_t)h->nw * 8;
   const double* hist = at<double>(h, h->M.hist);
-  for (long long k = 0; k < count; ++k) {
+  // the rows form at most two contiguous runs of the ring
+  for (long long k = 0; k < count;) {
     const long long r = (first + k) % H;
-    HIP_TRY(h, hipMemcpy(out + k * row, hist + r * row, row * 8, hipMemcpyDeviceToHost));
+    const long long run = std::min<long long>(count - k, H - r);
+    HIP_TRY(h, hipMemcpy(out + k * row, hist + r * row, (size_t)run * row * 8, hipMemcpyDeviceToHost));
+    k += run;
   }
   if (flags & 2) return fail(h, IBMLBM_EDIVERGED, "a perimeter system became singular");
   if (flags & 1) return fail(h, IBMLBM_EDIVERGED, "non-finite density seen on a check step");
@@ -947,6 +1098,14 @@ int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass) {
   return IBMLBM_OK;
 }
 
+int ibmlbm_set_stream(ibmlbm_t h, void* hip_stream) {
+  if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
+  HIP_TRY(h, hipStreamSynchronize(h->stream));
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->pin_pending = false;   // the last upload was read before the synchronisation
+  return IBMLBM_OK;
+}
+
 int ibmlbm_timing(ibmlbm_t h, int32_t enable) {
   if (!h) return fail(nullptr, IBMLBM_EINVAL, "null handle");
   if (enable > 0 && h->ev.empty()) {
@@ -983,6 +1142,8 @@ int ibmlbm_destroy(ibmlbm_t h) {
   if (!h) return IBMLBM_OK;
   hipError_t e = hipStreamSynchronize(h->stream);
   for (auto& ev : h->ev) (void)hipEventDestroy(ev);
+  if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
+  if (h->pin) (void)hipHostFree(h->pin);
   delete h;
   if (e != hipSuccess) return fail(nullptr, IBMLBM_EDEVICE, "stream error at destroy: %s", hipGetErrorString(e));
   return IBMLBM_OK;

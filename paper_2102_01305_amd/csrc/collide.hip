@@ -150,14 +150,12 @@ __device__ void reduce_forces(const CollideArgs& a) {
 
 // Every cell, one row per wave, 64 cells along x per wave, 4 waves per block.
 template <class St, bool IBM, bool FORCE, bool CHECK>
-__global__ void __launch_bounds__(kBlockX * kBlockRows)
-k_collide(CollideArgs a) {
+__device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a, int lb) {
   using T = typename St::T;
   const Geo& g = a.g;
   const T* __restrict__ S = static_cast<const T*>(a.src);
   T* __restrict__ D = static_cast<T*>(a.dst);
-  if (IBM && blockIdx.x == 0) reduce_forces(a);
-  const int lb = blockIdx.x;
+  if (IBM && lb == 0) reduce_forces(a);
   const int xc = lb % a.nxc;
   const int rg = lb / a.nxc;
   const int x = xc * kBlockX + threadIdx.x;
@@ -192,33 +190,48 @@ k_collide(CollideArgs a) {
 }
 
 template <class St, bool IBM, bool FORCE, bool CHECK>
-static hipError_t launch_collide_t(const CollideArgs& a, hipStream_t s) {
-  k_collide<St, IBM, FORCE, CHECK><<<a.nblocks, dim3(kBlockX, kBlockRows), 0, s>>>(a);
+__global__ void __launch_bounds__(kBlockX * kBlockRows)
+k_collide(Group gr) {
+  int lb;
+  const CollideArgs* a = static_cast<const CollideArgs*>(group_find(gr, lb));
+  collide_block<St, IBM, FORCE, CHECK>(*a, lb);
+}
+
+template <class St, bool IBM, bool FORCE, bool CHECK>
+static hipError_t launch_collide_t(const Group& g, int blocks, hipStream_t s) {
+  k_collide<St, IBM, FORCE, CHECK><<<blocks, dim3(kBlockX, kBlockRows), 0, s>>>(g);
   return hipGetLastError();
 }
 
 template <class St>
-static hipError_t launch_collide_s(bool ibm, bool force, bool check, const CollideArgs& a,
+static hipError_t launch_collide_s(bool ibm, bool force, bool check, const Group& g, int blocks,
                                    hipStream_t s) {
   const int key = (ibm ? 4 : 0) | (force ? 2 : 0) | (check ? 1 : 0);
   switch (key) {
-    case 0: return launch_collide_t<St, false, false, false>(a, s);
-    case 1: return launch_collide_t<St, false, false, true>(a, s);
-    case 2: return launch_collide_t<St, false, true, false>(a, s);
-    case 3: return launch_collide_t<St, false, true, true>(a, s);
-    case 4: return launch_collide_t<St, true, false, false>(a, s);
-    case 5: return launch_collide_t<St, true, false, true>(a, s);
-    case 6: return launch_collide_t<St, true, true, false>(a, s);
-    default: return launch_collide_t<St, true, true, true>(a, s);
+    case 0: return launch_collide_t<St, false, false, false>(g, blocks, s);
+    case 1: return launch_collide_t<St, false, false, true>(g, blocks, s);
+    case 2: return launch_collide_t<St, false, true, false>(g, blocks, s);
+    case 3: return launch_collide_t<St, false, true, true>(g, blocks, s);
+    case 4: return launch_collide_t<St, true, false, false>(g, blocks, s);
+    case 5: return launch_collide_t<St, true, false, true>(g, blocks, s);
+    case 6: return launch_collide_t<St, true, true, false>(g, blocks, s);
+    default: return launch_collide_t<St, true, true, true>(g, blocks, s);
   }
 }
 
-hipError_t launch_collide(int storage, bool ibm, bool force, bool check, const CollideArgs& a,
+hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
+                          const CollideArgs* const* host, const void* const* dev, int n,
                           hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  Group g;
+  int blocks[kMaxGroup];
+  for (int k = 0; k < n; ++k) blocks[k] = host[k]->nblocks;
+  const int total = group_fill(g, dev, blocks, n);
+  if (total == 0) return hipSuccess;
   switch (storage) {
-    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, a, s);
-    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, a, s);
-    default: return launch_collide_s<StBF16>(ibm, force, check, a, s);
+    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, g, total, s);
+    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, g, total, s);
+    default: return launch_collide_s<StBF16>(ibm, force, check, g, total, s);
   }
 }
 

@@ -14,7 +14,8 @@ constexpr int kMaxWings = 8;
 constexpr int kMaxPerim = 128;     // perimeter markers per foil (LDS of the inversion)
 constexpr int kBlockX = 64;        // collide block: 64 cells along x ...
 constexpr int kBlockRows = 4;      // ... times 4 rows, one row per wave
-constexpr int kFactorWindow = 64;  // steps whose perimeter factors are made at once
+constexpr int kFactorWindow = 64;  // steps whose perimeter factors (and launch arguments) are made at once
+constexpr int kMaxGroup = 64;      // solves in one grouped launch
 
 enum Bc { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
@@ -123,9 +124,21 @@ struct MarkerArgs {
   int* flags;                // bit 1: singular perimeter system
 };
 
-// launch wrappers (kernels.hip); all enqueue on `s` and return hipError_t
+// A grouped launch: the blocks of solve k are start[k] .. start[k+1]-1 and
+// read that solve's arguments from device memory at args[k].  One solve is a
+// group of one, so a solve runs the same code alone and in a group.
+struct Group {
+  int n;
+  int start[kMaxGroup + 1];
+  const void* args[kMaxGroup];
+};
+
+// launch wrappers (collide.hip, markers.hip); all enqueue on `s` and return
+// hipError_t.  `host[k]` is the host copy of the arguments that `dev[k]`
+// holds on the device (used for grid and LDS sizing only).
 hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
-                          const CollideArgs& a, hipStream_t s);
+                          const CollideArgs* const* host, const void* const* dev, int n,
+                          hipStream_t s);
 hipError_t launch_ghost(int storage, const Geo& g, const Phys& p, void* buf, hipStream_t s);
 hipError_t launch_init_eq(int storage, const Geo& g, const double* rho, const double* u,
                           void* dst, hipStream_t s);
@@ -133,7 +146,9 @@ hipError_t launch_moments(int storage, const Geo& g, const Phys& p, const void* 
                           float* out, hipStream_t s);
 hipError_t launch_mass_reduce(const double* part, int n, double ncells, double* out,
                               long long step, hipStream_t s);
-hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s);
-hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s);
+hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, int n, int count,
+                         hipStream_t s);
+hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void* const* dev, int n,
+                          hipStream_t s);
 
 }  // namespace ibmk

@@ -137,6 +137,33 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
   for (int i = 0; i < kQ; ++i) f[i] = RAW ? St::ldr(src[i]) : St::ld(src[i]);
 }
 
+// The solve a block of a grouped launch belongs to (binary search over the
+// block offsets, all in kernel arguments) and its block index within it.
+__device__ __forceinline__ const void* group_find(const Group& g, int& lb) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = g.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.start[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  lb = b - g.start[lo];
+  return g.args[lo];
+}
+
+// Block offsets of a grouped launch from per-solve block counts; returns the
+// total.
+inline int group_fill(Group& g, const void* const* dev, const int* blocks, int n) {
+  g.n = n;
+  int t = 0;
+  for (int k = 0; k < n; ++k) {
+    g.start[k] = t;
+    g.args[k] = dev[k];
+    t += blocks[k];
+  }
+  g.start[n] = t;
+  return t;
+}
+
 // Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
 __device__ __forceinline__ float feq_dev(int i, float drho, float rho, float ux, float uy,
                                          float uz, float usq) {

@@ -85,9 +85,9 @@ __device__ __forceinline__ double a1(const double* wp, int bp, const double* wq,
 // Gauss-Jordan (symmetric positive definite: no pivoting), FP64 in LDS.
 // These depend on the prescribed kinematics only, so they are computed for a
 // window of future steps at once, one block per (step, foil).
-__global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
+__device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
-  const int slot = blockIdx.x / a.nw, wi = blockIdx.x - slot * a.nw;
+  const int slot = lb / a.nw, wi = lb - slot * a.nw;
   const WingDev& w = a.w[wi];
   const int n = w.np;
   double* M = lds;              // n * n
@@ -152,13 +152,19 @@ __global__ void __launch_bounds__(256) k_factor(MarkerArgs a) {
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) out[e] = M[e];
 }
 
+__global__ void __launch_bounds__(256) k_factor(Group gr) {
+  int lb;
+  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
+  factor_block(*a, lb);
+}
+
 // rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
 // pre-collision state at every node of every foil's box, on every layer.
 // One wave per box row (y, z), lanes along x, so rows are wave-uniform.
 template <class St>
-__global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
+__device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int lb) {
   using T = typename St::T;
-  int R = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  int R = __builtin_amdgcn_readfirstlane((int)(lb * 4 + (threadIdx.x >> 6)));
   const int lane = threadIdx.x & 63;
   int wi = 0;
   while (wi < a.nw) {
@@ -188,6 +194,13 @@ __global__ void __launch_bounds__(256) k_band(MarkerArgs a) {
   }
 }
 
+template <class St>
+__global__ void __launch_bounds__(256) k_band(Group gr) {
+  int lb;
+  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
+  band_block<St>(*a, lb);
+}
+
 __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, int& wi) {
   wi = 0;
   while (wi + 1 < a.nw && blk >= a.w[wi].ns) {
@@ -203,10 +216,10 @@ __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, in
 // over the foil's box, kept in LDS; then one thread per marker sums its
 // 4 x 4 xy nodes.  B is also written column-major (marker, component, layer)
 // for the span solve.
-__global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
+__device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
   int wi;
-  const int s = find_layer_block(a, blockIdx.x, wi);
+  const int s = find_layer_block(a, lb, wi);
   const WingDev& w = a.w[wi];
   const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
   double* P = lds;                 // n * kPw
@@ -267,14 +280,20 @@ __global__ void __launch_bounds__(256) k_interp(MarkerArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_interp(Group gr) {
+  int lb;
+  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
+  interp_block(*a, lb);
+}
+
 // Block (foil, perimeter marker p): the span part of the minimum-norm solve,
 // T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
 // row of the circulant span factor.  Each thread makes four consecutive
 // outputs from a sliding window of G over one part of the s2 range; the
 // parts are added in a fixed order.  T is written layer-major.
-__global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
+__device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
-  int wi = 0, p = blockIdx.x;
+  int wi = 0, p = lb;
   while (wi + 1 < a.nw && p >= a.w[wi].np) {
     p -= a.w[wi].np;
     ++wi;
@@ -331,6 +350,12 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_span(Group gr) {
+  int lb;
+  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
+  span_block(*a, lb);
+}
+
 // Block (foil, span layer s): the perimeter part of the solve,
 // y(p) = sum_q M_xy^-1[p][q] T(q, s), du_B = y / dA (Eqs. 18-19); the body
 // force and moment of the layer, -2 rho_B y (Eq. 26), reduced in a fixed
@@ -339,11 +364,11 @@ __global__ void __launch_bounds__(256) k_span(MarkerArgs a) {
 // built in `a.copies` partial images, each added by one wave over the
 // markers p = copy (mod copies) in order, then summed copy by copy, so the
 // sums are the same on every run.
-__global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
+__device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
   __shared__ double red[4][256];
   int wi;
-  const int s = find_layer_block(a, blockIdx.x, wi);
+  const int s = find_layer_block(a, lb, wi);
   const WingDev& w = a.w[wi];
   const int n = w.np, ns = w.ns, cells = w.bw * w.bh, copies = a.copies;
   double* Mi = lds;                                  // n * n
@@ -422,56 +447,92 @@ __global__ void __launch_bounds__(256) k_layer(MarkerArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_layer(Group gr) {
+  int lb;
+  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
+  layer_block(*a, lb);
+}
+
 static hipError_t raise_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_factor(const MarkerArgs& a, int count, hipStream_t s) {
-  int maxnp = 0;
-  for (int k = 0; k < a.nw; ++k) maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, int n, int count,
+                         hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  int maxnp = 0, blocks[kMaxGroup];
+  for (int j = 0; j < n; ++j) {
+    const MarkerArgs& a = *host[j];
+    for (int k = 0; k < a.nw; ++k) maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+    blocks[j] = count * a.nw;
+  }
   const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_factor), lds);
   if (e != hipSuccess) return e;
-  k_factor<<<(unsigned)(count * a.nw), 256, lds, s>>>(a);
+  Group g;
+  const int total = group_fill(g, dev, blocks, n);
+  if (total == 0) return hipSuccess;
+  k_factor<<<(unsigned)total, 256, lds, s>>>(g);
   return hipGetLastError();
 }
 
-hipError_t launch_markers(int storage, const MarkerArgs& a, hipStream_t s) {
-  int maxnp = 0, layers = 0, perims = 0, maxcells = 0, ns = a.g.nz;
-  for (int k = 0; k < a.nw; ++k) {
-    maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
-    layers += a.w[k].ns;
-    perims += a.w[k].np;
-    const int c = a.w[k].bw * a.w[k].bh;
-    maxcells = c > maxcells ? c : maxcells;
+hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void* const* dev, int n,
+                          hipStream_t s) {
+  if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
+  int nb[kMaxGroup], nl[kMaxGroup], np[kMaxGroup];
+  size_t lds_i = 0, lds_l = 0, lds_s = 0;
+  for (int j = 0; j < n; ++j) {
+    const MarkerArgs& a = *host[j];
+    int maxnp = 0, layers = 0, perims = 0, maxcells = 0;
+    const int ns = a.g.nz;
+    for (int k = 0; k < a.nw; ++k) {
+      maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+      layers += a.w[k].ns;
+      perims += a.w[k].np;
+      const int c = a.w[k].bw * a.w[k].bh;
+      maxcells = c > maxcells ? c : maxcells;
+    }
+    const size_t li = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
+    const size_t ll = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
+                      (size_t)a.copies * maxcells * 3 * sizeof(float);
+    const int groups = (ns + 3) / 4;
+    int parts = 256 / groups;
+    parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+    const size_t ls = (5 + 3 * (size_t)parts) * (size_t)ns * sizeof(double);
+    lds_i = li > lds_i ? li : lds_i;
+    lds_l = ll > lds_l ? ll : lds_l;
+    lds_s = ls > lds_s ? ls : lds_s;
+    nb[j] = a.band_blocks;   // 4 box rows per block
+    nl[j] = layers;
+    np[j] = perims;
   }
-  const size_t lds_i = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
-  const size_t lds_l = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
-                       (size_t)a.copies * maxcells * 3 * sizeof(float);
-  const int groups = (ns + 3) / 4;
-  int parts = 256 / groups;
-  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
-  const size_t lds_s = (5 + 3 * (size_t)parts) * (size_t)ns * sizeof(double);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_span), lds_s);
   if (e != hipSuccess) return e;
-  const unsigned nb = (unsigned)a.band_blocks;   // 4 box rows per block
-  switch (storage) {
-    case ST_F32: k_band<StF32><<<nb, 256, 0, s>>>(a); break;
-    case ST_F16: k_band<StF16><<<nb, 256, 0, s>>>(a); break;
-    default: k_band<StBF16><<<nb, 256, 0, s>>>(a); break;
+  Group g;
+  int total = group_fill(g, dev, nb, n);
+  if (total > 0) {
+    switch (storage) {
+      case ST_F32: k_band<StF32><<<total, 256, 0, s>>>(g); break;
+      case ST_F16: k_band<StF16><<<total, 256, 0, s>>>(g); break;
+      default: k_band<StBF16><<<total, 256, 0, s>>>(g); break;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
+  total = group_fill(g, dev, nl, n);
+  if (total == 0) return hipSuccess;
+  k_interp<<<total, 256, lds_i, s>>>(g);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_interp<<<layers, 256, lds_i, s>>>(a);
+  const int tp = group_fill(g, dev, np, n);
+  k_span<<<tp, 256, lds_s, s>>>(g);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_span<<<perims, 256, lds_s, s>>>(a);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_layer<<<layers, 256, lds_l, s>>>(a);
+  group_fill(g, dev, nl, n);
+  k_layer<<<total, 256, lds_l, s>>>(g);
   return hipGetLastError();
 }
 

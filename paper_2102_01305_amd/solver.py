@@ -131,6 +131,11 @@ class Solver:
             raise ValueError("fdist must hold 19*nx*ny*nz values")
         L.check(self.lib.ibmlbm_init_fields(self.h, _dptr(r), _dptr(v), _dptr(f), int(step0)), self.h)
 
+    def set_stream(self, stream):
+        """Enqueue this solve's work on `stream` from now on (a torch stream)."""
+        L.check(self.lib.ibmlbm_set_stream(self.h, C.c_void_p(stream.cuda_stream)), self.h)
+        self.stream = stream
+
     def step(self, n=1):
         L.check(self.lib.ibmlbm_step(self.h, int(n)), self.h)
 
@@ -184,6 +189,11 @@ class Solver:
                     marker_ms=m.value)
 
     @property
+    def footprint(self):
+        """Device bytes this solve holds (its workspace)."""
+        return self.nbytes
+
+    @property
     def bytes_per_cell(self):
         return int(self.lib.ibmlbm_bytes_per_cell(self.h))
 
@@ -197,3 +207,24 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def workspace_bytes(bx, wings=(), storage="fp32", check_interval=0, history_steps=1024):
+    """Device bytes a solve of this description needs (0 if it is invalid)."""
+    lib = L.load()
+    cfg = make_config(bx, storage, check_interval, history_steps)
+    arr = make_wings(list(wings))
+    return int(lib.ibmlbm_workspace_bytes(C.byref(cfg), len(wings), arr))
+
+
+def step_batch(solvers, n=1):
+    """Advance every solver by n steps in lock step, each stage of a step as
+    one grouped launch over all of them (they must share one stream)."""
+    solvers = list(solvers)
+    if not solvers:
+        return
+    lib = solvers[0].lib
+    arr = (L.Handle * len(solvers))(*[s.h for s in solvers])
+    rc = lib.ibmlbm_step_batch(arr, len(solvers), int(n))
+    if rc != L.OK:
+        raise L.IbmlbmError(rc, lib.ibmlbm_last_error(None).decode())
