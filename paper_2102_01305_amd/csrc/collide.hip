@@ -156,11 +156,24 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   const T* __restrict__ S = static_cast<const T*>(a.src);
   T* __restrict__ D = static_cast<T*>(a.dst);
   if (IBM && lb == 0) reduce_forces(a);
-  const int xc = lb % a.nxc;
-  const int rg = lb / a.nxc;
+  // Waves to (64-cell chunk, row).  FP32: a block is one chunk of 4
+  // consecutive rows.  16-bit storage: waves run along x first, so the
+  // chunks of a row sit in one block and the cache line each chunk shares
+  // with its neighbour (the x -/+ 1 pulls) is fetched from memory once; at
+  // 2 bytes a wave reads a single line per population row, so these shared
+  // lines are a large part of its reads.
+  int xc, row;
+  if (sizeof(T) == 2) {
+    const int gw = lb * kBlockRows + (int)threadIdx.y;
+    xc = gw % a.nxc;
+    row = gw / a.nxc;
+  } else {
+    xc = lb % a.nxc;
+    row = (lb / a.nxc) * kBlockRows + (int)threadIdx.y;
+  }
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
-  const int row = __builtin_amdgcn_readfirstlane(rg * kBlockRows + (int)threadIdx.y);
+  row = __builtin_amdgcn_readfirstlane(row);
   const bool active = x < g.nx && row < g.ny * g.nz;
   double dm = 0.0;
   bool bad = false;
