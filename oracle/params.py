@@ -35,6 +35,14 @@ def plate(re, u_inf, chord):
     return dict(nu=nu, tau=tau_from_nu(nu))
 
 
+def figure_eight(re, u_tip, chord, a0):
+    """Figure-eight hovering (Sec. 3.2): Re = U_tip c / nu with the maximum
+    centre speed U_tip = pi f A0 (Eq. 22), so the period is T = 1/f =
+    pi A0 / U_tip steps."""
+    nu = u_tip * chord / re
+    return dict(nu=nu, tau=tau_from_nu(nu), period_steps=math.pi * a0 / u_tip)
+
+
 def complete_case(bx, wings, phys):
     """Fill tau, inlet velocity, reference velocity and wing periods from the
     raw physics of a workload description.  Returns new (box, wings)."""
@@ -51,6 +59,12 @@ def complete_case(bx, wings, phys):
         bx["tau"] = p["tau"]
         bx["u_in"] = [p["u_inf"], 0.0, 0.0]
         bx["u_ref"] = p["u_tip"]
+        for w in wings:
+            w["period_steps"] = p["period_steps"]
+    elif phys["kind"] == "figure_eight":
+        p = figure_eight(phys["re"], phys["u_tip"], phys["chord"], phys["a0"])
+        bx["tau"] = p["tau"]
+        bx["u_ref"] = phys["u_tip"]
         for w in wings:
             w["period_steps"] = p["period_steps"]
     else:

@@ -42,6 +42,13 @@ def complete_case(bx, wings, phys):
         bx["u_ref"] = p["u_tip"]
         for w in wings:
             w["period_steps"] = p["period_steps"]
+    elif phys["kind"] == "figure_eight":
+        # Re = U_tip c / nu, U_tip = pi f A0 (Eq. 22): period pi A0 / U_tip
+        nu = phys["u_tip"] * phys["chord"] / phys["re"]
+        bx["tau"] = 3.0 * nu + 0.5
+        bx["u_ref"] = phys["u_tip"]
+        for w in wings:
+            w["period_steps"] = math.pi * phys["a0"] / phys["u_tip"]
     else:
         raise ValueError(phys["kind"])
     return bx, wings

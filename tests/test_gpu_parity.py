@@ -210,3 +210,31 @@ def test_bad_config_rejected():
     far = [dict(wg[0], hinge=[3.0, 15.5])]
     with pytest.raises(L.IbmlbmError):
         Solver(bx, far)
+
+
+def test_figure_eight_parity():
+    """Hovering wing on the figure-eight stroke (Eq. 20-22: translation along
+    the inclined stroke plane plus pitch about the centre), 64x64x8 closed
+    box, 80 steps from t = T/8 where both motions are under way: u and C_L
+    against the oracle."""
+    bx, wg, ph = WL.figure_eight_case()
+    from oracle import params
+    T = params.complete_case(bx, wg, ph)[1][0]["period_steps"]
+    t0 = int(T / 8)
+    _say("figure-eight 64x64x8, c=15, 80 steps from", t0)
+    u0 = WL.velocity_noise((bx["nz"], bx["ny"], bx["nx"]), 11)
+    gpu = gpu_solver(bx, wg, ph, u0=u0, step0=t0)
+    ora = oracle_sim(bx, wg, ph, u0=u0, step0=t0)
+    gpu.step(80)
+    ora.run(80)
+    rho_o, u_o = ora.fields()
+    err = l2rel(gpu.fields("u"), u_o)
+    print("L2 rel u", err)
+    assert err <= 1e-5
+    fg = gpu.forces(t0, 80)
+    fo = ora.forces()
+    for k in (4, 5):
+        d = np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max()
+        print("coefficient", k, "max rel", d)
+        assert d <= 1e-3
+    gpu.close()

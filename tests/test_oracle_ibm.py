@@ -260,3 +260,29 @@ def test_lattice_params_clap_fling():
     assert abs(p["period_steps"] - 1675.516081914556) < 1e-9
     p = params.plate(100.0, 0.02, 10.0)
     assert abs(p["tau"] - 0.506) < 1e-14
+
+
+def test_figure_eight_kinematics_closed_form():
+    """Eq. 20-22 at t = 0 and T/4: the centre sits at +A0/2 along the stroke
+    plane, then crosses the hinge at the maximum speed pi A0 / T, which is
+    the tip speed that defines Re; alpha goes from pi/4 to 0."""
+    from oracle import params
+    from oracle.ibm import alpha, hinge_motion
+
+    bx, wg, ph = WL.figure_eight_case()
+    ob, ow = params.complete_case(bx, wg, ph)
+    w = ow[0]
+    T = w["period_steps"]
+    a0 = ph["a0"]
+    beta = w["trans_angle"]
+    e = np.array([math.cos(beta), math.sin(beta)])
+    h0 = np.array(w["hinge"])
+    X, V = hinge_motion(w, 0.0)
+    assert np.allclose(X, h0 + 0.5 * a0 * e, atol=1e-12)
+    assert np.allclose(V, 0.0, atol=1e-15)
+    X, V = hinge_motion(w, T / 4.0)
+    assert np.allclose(X, h0, atol=1e-12)
+    assert np.allclose(V, -ph["u_tip"] * e, rtol=1e-12, atol=1e-15)
+    assert alpha(w, 0.0)[0] == pytest.approx(math.pi / 4.0, abs=1e-15)
+    assert alpha(w, T / 4.0)[0] == pytest.approx(0.0, abs=1e-14)
+    assert ob["tau"] == pytest.approx(3.0 * ph["u_tip"] * ph["chord"] / ph["re"] + 0.5, rel=1e-15)

@@ -81,6 +81,28 @@ def plate_case(nx=64, ny=32, nz=32, chord=10.0, aspect=5.0, u_inf=0.02, re=100.0
     return bx, wg, phys
 
 
+def figure_eight_case(nx=64, ny=64, nz=8, chord=15.0, aspect=7.5, a0_over_c=2.5,
+                      beta=math.pi / 3.0, re=75.0, u_tip=0.05):
+    """Hovering elliptic wing on the figure-eight stroke of Sec. 3.2: the
+    centre sweeps along a stroke plane inclined at beta with amplitude A0/2
+    (Eq. 20) while the wing pitches about its centre with
+    alpha = pi/4 - pi/4 sin(2 pi t / T) (Eq. 21).  Closed box (walls in x
+    and y), periodic span.  Re = U_tip c / nu with U_tip = pi f A0 (Eq. 22);
+    the lattice tip speed u_tip fixes f, so each side maps (re, u_tip,
+    chord, A0) to tau and the period itself.
+    """
+    a0 = a0_over_c * chord
+    phys = dict(kind="figure_eight", re=re, u_tip=u_tip, chord=chord, a0=a0)
+    bx = dict(nx=nx, ny=ny, nz=nz, bc=[WALL, WALL, WALL, WALL, PERIODIC, PERIODIC],
+              u_in=[0.0, 0.0, 0.0], rho_out=1.0, body_force=[0.0, 0.0, 0.0],
+              u_ref=u_tip, area_ref=chord * nz)
+    centre = (nx / 2.0 - 0.5, ny / 2.0 - 0.5)
+    wg = [wing(chord, chord / aspect, centre, 0.5, beta, 1.0, ALPHA_SIN,
+               alpha_mean=math.pi / 4.0, alpha_amp=-math.pi / 4.0, period_steps=None,
+               trans_amp=0.5 * a0, trans_angle=beta)]
+    return bx, wg, phys
+
+
 def clap_gap(chord, aspect=5.0):
     """Distance between the two chord lines at the hinges.
 
