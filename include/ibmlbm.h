@@ -57,10 +57,24 @@ enum {
 };
 
 /* Face boundary kinds; faces are ordered -x, +x, -y, +y, -z, +z.
- * PERIODIC must be given on both faces of an axis.  VELOCITY and PRESSURE
- * are allowed on x faces only (Sec. 2.1: uniform-velocity inflow,
- * atmospheric-pressure outflow; walls by half-way bounce-back). */
-enum { IBMLBM_BC_PERIODIC = 0, IBMLBM_BC_WALL = 1, IBMLBM_BC_VELOCITY = 2, IBMLBM_BC_PRESSURE = 3 };
+ * PERIODIC must be given on both faces of an axis.  The inflow/outflow
+ * kinds are allowed on x faces only (Sec. 2.1: uniform-velocity inflow,
+ * atmospheric-pressure outflow; walls by half-way bounce-back).
+ * VELOCITY / PRESSURE: the populations entering through the face come from
+ * a ghost layer at equilibrium with the prescribed velocity (density of the
+ * boundary cell) or the prescribed density (velocity of the boundary cell).
+ * ZH_VELOCITY / ZH_PRESSURE: the Zou-He scheme the paper names for its
+ * cylinder case (Sec. 3.1, its ref. [21]): the entering populations of each
+ * boundary cell are rebuilt from its known ones so that its density and
+ * momentum take the prescribed velocity (density from the known
+ * populations) or the prescribed density (transverse velocity zero), with
+ * non-equilibrium bounce-back of the normal population and a transverse
+ * momentum correction (D3Q19 form).  Boundary cells whose entering links
+ * also touch a y or z wall keep the equilibrium ghost rule. */
+enum {
+  IBMLBM_BC_PERIODIC = 0, IBMLBM_BC_WALL = 1, IBMLBM_BC_VELOCITY = 2, IBMLBM_BC_PRESSURE = 3,
+  IBMLBM_BC_ZH_VELOCITY = 4, IBMLBM_BC_ZH_PRESSURE = 5
+};
 
 /* Storage of the distributions.  FP32 stores f_i - w_i in float; the
  * FP16/BF16 forms store f_i - w_i in 16 bits.  Collision arithmetic is FP32

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import numpy as np
 
-PERIODIC, WALL, VELOCITY, PRESSURE = 0, 1, 2, 3
+PERIODIC, WALL, VELOCITY, PRESSURE, ZH_VELOCITY, ZH_PRESSURE = 0, 1, 2, 3, 4, 5
 
 # D3Q19 velocities: rest, 6 face neighbours, 12 edge neighbours.
 C = np.array([
@@ -84,7 +84,11 @@ def stream(S, bc, u_in, rho_out):
         velocity u_in and of the density of S at the adjacent boundary cell;
       * across a PRESSURE face (x only): equilibrium of density rho_out and of
         the velocity of S at the adjacent boundary cell
-        (Sec. 2.1: uniform-velocity inflow, atmospheric-pressure outflow).
+        (Sec. 2.1: uniform-velocity inflow, atmospheric-pressure outflow);
+      * ZH_VELOCITY / ZH_PRESSURE faces (x only): the Zou-He scheme of the
+        paper's cylinder case (Sec. 3.1), applied by `zou_he` after the pull;
+        boundary cells whose entering links touch a y or z wall keep the
+        equilibrium ghost of VELOCITY / PRESSURE.
     bc lists the six faces (-x, +x, -y, +y, -z, +z).
     """
     q, nz, ny, nx = S.shape
@@ -99,10 +103,10 @@ def stream(S, bc, u_in, rho_out):
     ghost = {}
     for face, bxc in ((0, 0), (1, nx - 1)):
         kind = bc[face]
-        if kind == VELOCITY:
+        if kind in (VELOCITY, ZH_VELOCITY):
             rg = rhoS[:, :, bxc]
             ug = np.broadcast_to(u_in[:, None, None], (3, nz, ny))
-        elif kind == PRESSURE:
+        elif kind in (PRESSURE, ZH_PRESSURE):
             rg = np.full((nz, ny), float(rho_out))
             ug = momS[:, :, :, bxc] / rhoS[None, :, :, bxc]
         else:
@@ -132,4 +136,44 @@ def stream(S, bc, u_in, rho_out):
             if face in ghost:
                 val = np.where(mask, ghost[face][i][sz, sy], val)
         f[i] = np.where(wall, S[OPP[i]], val)
+    for face in (0, 1):
+        if bc[face] in (ZH_VELOCITY, ZH_PRESSURE):
+            zou_he(f, bc, face, u_in, rho_out)
     return f
+
+
+def zou_he(f, bc, face, u_in, rho_out):
+    """Zou-He boundary cells of x face `face` (0: x = 0, 1: x = nx - 1), in
+    place on the streamed f.  With n = +1 on the -x face and -1 on the +x
+    face, the unknown populations are those with c_x = n.  Known sums:
+    K = sum_{c_x=0} f + 2 sum_{c_x=-n} f.  Mass and normal momentum give
+    rho (1 - n u_x) = K, so
+      velocity face: u prescribed, rho = K / (1 - n u_x);
+      pressure face: rho = rho_out, u_x = n (1 - K / rho), u_y = u_z = 0.
+    Each unknown is its opposite plus the equilibrium difference,
+      f_i = f_opp(i) + 2 w_i rho (c_i . u) / c_s^2 - c_iy N_y - c_iz N_z,
+    where N_t = (1/2) sum_{c_x=0} c_t f - rho u_t / 3 fixes the transverse
+    momentum to rho u_t.  Cells whose entering links touch a y or z wall are
+    left as streamed (equilibrium ghost)."""
+    _, nz, ny, nx = f.shape
+    xb = 0 if face == 0 else nx - 1
+    n = 1 if face == 0 else -1
+    ys = slice(0, ny) if bc[2] == PERIODIC else slice(1, ny - 1)
+    zs = slice(0, nz) if bc[4] == PERIODIC else slice(1, nz - 1)
+    fb = f[:, zs, ys, xb]                     # (19, z, y) view of the boundary cells
+    zero = C[:, 0] == 0
+    K = fb[zero].sum(axis=0) + 2.0 * fb[C[:, 0] == -n].sum(axis=0)
+    if bc[face] == ZH_VELOCITY:
+        u = [float(u_in[0]), float(u_in[1]), float(u_in[2])]
+        rho = K / (1.0 - n * u[0])
+        ux, uy, uz = (np.full_like(K, v) for v in u)
+    else:
+        rho = np.full_like(K, float(rho_out))
+        ux = n * (1.0 - K / rho)
+        uy = np.zeros_like(K)
+        uz = np.zeros_like(K)
+    Ny = 0.5 * (C[zero, 1][:, None, None] * fb[zero]).sum(axis=0) - rho * uy / 3.0
+    Nz = 0.5 * (C[zero, 2][:, None, None] * fb[zero]).sum(axis=0) - rho * uz / 3.0
+    for i in np.nonzero(C[:, 0] == n)[0]:
+        cu = C[i, 0] * ux + C[i, 1] * uy + C[i, 2] * uz
+        fb[i] = fb[OPP[i]] + 2.0 * W[i] * rho * cu / CS2 - C[i, 1] * Ny - C[i, 2] * Nz

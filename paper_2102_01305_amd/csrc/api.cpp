@@ -32,7 +32,7 @@ struct LatticeLayout {
   size_t total = 0;      // elements of the slabs of one state buffer
   size_t goff = 0;       // byte offset of the ghost records in a state buffer
   size_t N = 0;
-  int nxc = 0, nblocks = 0;
+  int nxc = 0, nblocks = 0, face_blocks = 0;
   Region fA, fB, mass_part, diag, argtab;
   size_t end = 0;
 };
@@ -131,8 +131,8 @@ int validate_config(const ibmlbm_config* c, std::string& why) {
   if (c->nx < 4 || c->ny < 4 || c->nz < 4) { why = "nx, ny, nz must each be >= 4"; return IBMLBM_EINVAL; }
   if ((long long)c->nx * c->ny * c->nz > (1LL << 34)) { why = "box too large"; return IBMLBM_EINVAL; }
   for (int f = 0; f < 6; ++f) {
-    if (c->bc[f] < 0 || c->bc[f] > 3) { snprintf(b, sizeof b, "bc[%d] unknown", f); why = b; return IBMLBM_EINVAL; }
-    if (f >= 2 && (c->bc[f] == IBMLBM_BC_VELOCITY || c->bc[f] == IBMLBM_BC_PRESSURE)) {
+    if (c->bc[f] < 0 || c->bc[f] > 5) { snprintf(b, sizeof b, "bc[%d] unknown", f); why = b; return IBMLBM_EINVAL; }
+    if (f >= 2 && c->bc[f] >= IBMLBM_BC_VELOCITY) {
       why = "VELOCITY/PRESSURE faces are supported on x faces only";
       return IBMLBM_EINVAL;
     }
@@ -162,13 +162,15 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   L.N = (size_t)c->nx * c->ny * c->nz;
   L.nxc = (c->nx + kBlockX - 1) / kBlockX;
   L.nblocks = L.nxc * ((c->ny * c->nz + kBlockRows - 1) / kBlockRows);
+  const int zh_faces = (c->bc[0] >= IBMLBM_BC_ZH_VELOCITY) + (c->bc[1] >= IBMLBM_BC_ZH_VELOCITY);
+  L.face_blocks = (int)(((long long)zh_faces * c->ny * c->nz + 255) / 256);
   size_t o = 0;
   auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + bytes); };
   L.goff = align256(L.total * L.es);
   const size_t state = L.goff + 2 * (size_t)c->ny * c->nz * 32;
   take(L.fA, state);
   take(L.fB, state);
-  take(L.mass_part, (size_t)L.nblocks * sizeof(double));
+  take(L.mass_part, (size_t)(L.nblocks + L.face_blocks) * sizeof(double));
   take(L.diag, 64);
   take(L.argtab, (size_t)kFactorWindow * kArgSlotBytes);
   L.end = o;
@@ -436,7 +438,11 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
     // every support node floor(X)-1 .. floor(X)+2 stays inside the box in x
     // and y (also on periodic axes: the node boxes of a foil do not wrap)
     const double reach = geo[k].rmax + std::fabs(x.trans_amp);
-    if (x.hinge[0] - reach < 1.0 || x.hinge[0] + reach >= c.nx - 2.0) {
+    // node boxes (support plus one spare cell) stay off Zou-He faces, whose
+    // boundary cells are rebuilt after streaming
+    const double xlo = c.bc[0] >= IBMLBM_BC_ZH_VELOCITY ? 4.0 : 1.0;
+    const double xhi = c.bc[1] >= IBMLBM_BC_ZH_VELOCITY ? 5.0 : 2.0;
+    if (x.hinge[0] - reach < xlo || x.hinge[0] + reach >= c.nx - xhi) {
       snprintf(b, sizeof b, "foil %d: marker supports may leave the box along x", k);
       why = b;
       return IBMLBM_EINVAL;
@@ -586,6 +592,7 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     ma.wz[0] = delta_h(1.5); ma.wz[1] = delta_h(0.5); ma.wz[2] = delta_h(0.5); ma.wz[3] = delta_h(1.5);
   }
   ca.nblocks = L.nblocks;
+  ca.face_blocks = L.face_blocks;
   ca.mass_part = at<double>(h, L.mass_part);
   ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
   void* A = h->ws + L.fA.off;
@@ -769,7 +776,8 @@ int run_steps(ibmlbm_t* hs, int n, int steps) {
       const ibmlbm_config& c = h->cfg;
       const long long s = h->step;
       if (c.check_interval > 0 && ((s + 1) % c.check_interval == 0))
-        HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks, (double)h->L.N,
+        HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks + h->L.face_blocks,
+                                      (double)h->L.N,
                                       reinterpret_cast<double*>(h->ws + h->L.diag.off), s + 1, st));
       h->cur_is_A = !h->cur_is_A;
       h->step = s + 1;

@@ -32,7 +32,7 @@ __device__ __forceinline__ bool in_box(const FoilBox& b, int x, int y) {
 // (kS f~): the moments, the equilibrium (Eq. 4, with rho scaled) and the
 // Guo term (Eq. 8, with F scaled) are linear in the distributions, and kS is
 // a power of two, so the result is the same as in units of f~.
-template <class St, bool IBM, bool FORCE>
+template <class St, bool IBM, bool FORCE, bool ZH = false>
 __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typename St::T* __restrict__ S,
                                               typename St::T* __restrict__ D, int x, int y, int z) {
   using T = typename St::T;
@@ -40,6 +40,7 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   const Geo& g = a.g;
   float f[kQ];
   pull19<St, true>(S, g, x, y, z, f);
+  if (ZH) zou_he<St, true>(g, a.p, x, y, z, f);
   float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;   // kS drho, kS j
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {
@@ -150,11 +151,12 @@ __device__ void reduce_forces(const CollideArgs& a) {
 
 // Every cell, one row per wave, 64 cells along x per wave, 4 waves per block.
 template <class St, bool IBM, bool FORCE, bool CHECK>
-__device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a, int lb) {
+__device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a, int lb,
+                                              const void* src, void* dst) {
   using T = typename St::T;
   const Geo& g = a.g;
-  const T* __restrict__ S = static_cast<const T*>(a.src);
-  T* __restrict__ D = static_cast<T*>(a.dst);
+  const T* __restrict__ S = static_cast<const T*>(src);
+  T* __restrict__ D = static_cast<T*>(dst);
   if (IBM && lb == 0) reduce_forces(a);
   // Waves to (64-cell chunk, row).  FP32: a block is one chunk of 4
   // consecutive rows.  16-bit storage: waves run along x first, so the
@@ -174,7 +176,9 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
   row = __builtin_amdgcn_readfirstlane(row);
-  const bool active = x < g.nx && row < g.ny * g.nz;
+  // cells on a Zou-He face are left to the face launch
+  const bool zh = (x == 0 && g.bclo >= BC_ZH_VELOCITY) || (x == g.nx - 1 && g.bchi >= BC_ZH_VELOCITY);
+  const bool active = x < g.nx && row < g.ny * g.nz && !zh;
   double dm = 0.0;
   bool bad = false;
   if (active) {
@@ -202,33 +206,82 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   }
 }
 
+// A grouped collide launch also carries each solve's state buffers as
+// kernel arguments, so the compiler knows they are global memory.
+struct CollideGroup {
+  Group g;
+  const void* src[kMaxGroup];
+  void* dst[kMaxGroup];
+};
+
 template <class St, bool IBM, bool FORCE, bool CHECK>
 __global__ void __launch_bounds__(kBlockX * kBlockRows)
-k_collide(Group gr) {
+k_collide(CollideGroup gr) {
   int lb;
-  const CollideArgs* a = static_cast<const CollideArgs*>(group_find(gr, lb));
-  collide_block<St, IBM, FORCE, CHECK>(*a, lb);
+  const int k = group_index(gr.g, lb);
+  const CollideArgs* a = static_cast<const CollideArgs*>(gr.g.args[k]);
+  collide_block<St, IBM, FORCE, CHECK>(*a, lb, gr.src[k], gr.dst[k]);
+}
+
+// The cells of the Zou-He faces, one thread per (face, y, z), after the
+// collide launch of the same step (disjoint cells of the same states).
+template <class St, bool IBM, bool FORCE, bool CHECK>
+__global__ void __launch_bounds__(256) k_collide_face(CollideGroup gr) {
+  using T = typename St::T;
+  int lb;
+  const int k = group_index(gr.g, lb);
+  const CollideArgs& a = *static_cast<const CollideArgs*>(gr.g.args[k]);
+  const Geo& g = a.g;
+  const int rows = g.ny * g.nz;
+  const int nf = (g.bclo >= BC_ZH_VELOCITY) + (g.bchi >= BC_ZH_VELOCITY);
+  const int t = lb * 256 + (int)threadIdx.x;
+  double dm = 0.0;
+  bool bad = false;
+  if (t < nf * rows) {
+    const int face = t / rows, r = t - face * rows;
+    const bool lo_face = face == 0 && g.bclo >= BC_ZH_VELOCITY;
+    const int x = lo_face ? 0 : g.nx - 1;
+    const int z = r / g.ny, y = r - z * g.ny;
+    const float drho = collide_cell<St, IBM, FORCE, true>(a, static_cast<const T*>(gr.src[k]),
+                                                          static_cast<T*>(gr.dst[k]), x, y, z);
+    dm = (double)drho;
+    bad = !isfinite(drho);
+  }
+  if (CHECK) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dm += __shfl_xor(dm, off);
+    __shared__ double part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dm;
+    if (bad) atomicOr(a.flags, 1);
+    __syncthreads();
+    if (threadIdx.x == 0) a.mass_part[a.nblocks + lb] = part[0] + part[1] + part[2] + part[3];
+  }
 }
 
 template <class St, bool IBM, bool FORCE, bool CHECK>
-static hipError_t launch_collide_t(const Group& g, int blocks, hipStream_t s) {
+static hipError_t launch_collide_t(const CollideGroup& g, int blocks, const CollideGroup& gf,
+                                   int face_blocks, hipStream_t s) {
   k_collide<St, IBM, FORCE, CHECK><<<blocks, dim3(kBlockX, kBlockRows), 0, s>>>(g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || face_blocks == 0) return e;
+  k_collide_face<St, IBM, FORCE, CHECK><<<face_blocks, 256, 0, s>>>(gf);
   return hipGetLastError();
 }
 
 template <class St>
-static hipError_t launch_collide_s(bool ibm, bool force, bool check, const Group& g, int blocks,
+static hipError_t launch_collide_s(bool ibm, bool force, bool check, const CollideGroup& g,
+                                   int blocks, const CollideGroup& gf, int face_blocks,
                                    hipStream_t s) {
   const int key = (ibm ? 4 : 0) | (force ? 2 : 0) | (check ? 1 : 0);
   switch (key) {
-    case 0: return launch_collide_t<St, false, false, false>(g, blocks, s);
-    case 1: return launch_collide_t<St, false, false, true>(g, blocks, s);
-    case 2: return launch_collide_t<St, false, true, false>(g, blocks, s);
-    case 3: return launch_collide_t<St, false, true, true>(g, blocks, s);
-    case 4: return launch_collide_t<St, true, false, false>(g, blocks, s);
-    case 5: return launch_collide_t<St, true, false, true>(g, blocks, s);
-    case 6: return launch_collide_t<St, true, true, false>(g, blocks, s);
-    default: return launch_collide_t<St, true, true, true>(g, blocks, s);
+    case 0: return launch_collide_t<St, false, false, false>(g, blocks, gf, face_blocks, s);
+    case 1: return launch_collide_t<St, false, false, true>(g, blocks, gf, face_blocks, s);
+    case 2: return launch_collide_t<St, false, true, false>(g, blocks, gf, face_blocks, s);
+    case 3: return launch_collide_t<St, false, true, true>(g, blocks, gf, face_blocks, s);
+    case 4: return launch_collide_t<St, true, false, false>(g, blocks, gf, face_blocks, s);
+    case 5: return launch_collide_t<St, true, false, true>(g, blocks, gf, face_blocks, s);
+    case 6: return launch_collide_t<St, true, true, false>(g, blocks, gf, face_blocks, s);
+    default: return launch_collide_t<St, true, true, true>(g, blocks, gf, face_blocks, s);
   }
 }
 
@@ -236,15 +289,21 @@ hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
                           const CollideArgs* const* host, const void* const* dev, int n,
                           hipStream_t s) {
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  Group g;
-  int blocks[kMaxGroup];
-  for (int k = 0; k < n; ++k) blocks[k] = host[k]->nblocks;
-  const int total = group_fill(g, dev, blocks, n);
+  CollideGroup g, gf;
+  int blocks[kMaxGroup], fblocks[kMaxGroup];
+  for (int k = 0; k < n; ++k) {
+    blocks[k] = host[k]->nblocks;
+    fblocks[k] = host[k]->face_blocks;
+    g.src[k] = gf.src[k] = host[k]->src;
+    g.dst[k] = gf.dst[k] = host[k]->dst;
+  }
+  const int total = group_fill(g.g, dev, blocks, n);
+  const int ftotal = group_fill(gf.g, dev, fblocks, n);
   if (total == 0) return hipSuccess;
   switch (storage) {
-    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, g, total, s);
-    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, g, total, s);
-    default: return launch_collide_s<StBF16>(ibm, force, check, g, total, s);
+    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, g, total, gf, ftotal, s);
+    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, g, total, gf, ftotal, s);
+    default: return launch_collide_s<StBF16>(ibm, force, check, g, total, gf, ftotal, s);
   }
 }
 
@@ -322,6 +381,7 @@ __global__ void k_moments(Geo g, Phys p, const typename St::T* S, float* out) {
   const int y = (int)(r % g.ny), z = (int)(r / g.ny);
   float f[kQ];
   pull19<St>(S, g, x, y, z, f);
+  zou_he<St, false>(g, p, x, y, z, f);
   float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
   for (int i = 0; i < kQ; ++i) {

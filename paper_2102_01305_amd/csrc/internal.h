@@ -17,7 +17,8 @@ constexpr int kBlockRows = 4;      // ... times 4 rows, one row per wave
 constexpr int kFactorWindow = 64;  // steps whose perimeter factors (and launch arguments) are made at once
 constexpr int kMaxGroup = 64;      // solves in one grouped launch
 
-enum Bc { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_PRESSURE = 3 };
+enum Bc { BC_PERIODIC = 0, BC_WALL = 1, BC_VELOCITY = 2, BC_PRESSURE = 3, BC_ZH_VELOCITY = 4,
+          BC_ZH_PRESSURE = 5 };
 enum Storage { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
 
 // FP16 storage keeps 2^12 (f_i - w_i): a power of two, so the scaling is
@@ -68,7 +69,8 @@ struct CollideArgs {
   float wz[4];               // span weights delta(1.5), delta(0.5), delta(0.5), delta(1.5)
   int nxc;                   // 64-wide chunks along x
   int nblocks;               // row groups of 4 rows x 64 cells
-  double* mass_part;         // per-block partial sums (check steps)
+  int face_blocks;           // blocks of the Zou-He face launch (0: no such face)
+  double* mass_part;         // per-block partial sums (check steps); face blocks after nblocks
   int* flags;                // bit 0: non-finite density seen
   // force reduction by block 0 on steps with foils
   const double* fpart;       // [nw][nz][4] layer forces and moments

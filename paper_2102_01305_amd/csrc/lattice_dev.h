@@ -139,7 +139,7 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
 
 // The solve a block of a grouped launch belongs to (binary search over the
 // block offsets, all in kernel arguments) and its block index within it.
-__device__ __forceinline__ const void* group_find(const Group& g, int& lb) {
+__device__ __forceinline__ int group_index(const Group& g, int& lb) {
   const int b = (int)blockIdx.x;
   int lo = 0, hi = g.n - 1;
   while (lo < hi) {
@@ -147,7 +147,10 @@ __device__ __forceinline__ const void* group_find(const Group& g, int& lb) {
     if (g.start[mid] <= b) lo = mid; else hi = mid - 1;
   }
   lb = b - g.start[lo];
-  return g.args[lo];
+  return lo;
+}
+__device__ __forceinline__ const void* group_find(const Group& g, int& lb) {
+  return g.args[group_index(g, lb)];
 }
 
 // Block offsets of a grouped launch from per-solve block counts; returns the
@@ -162,6 +165,62 @@ inline int group_fill(Group& g, const void* const* dev, const int* blocks, int n
   }
   g.start[n] = t;
   return t;
+}
+
+// Zou-He faces: rebuild the populations entering through an x face at a
+// boundary cell from its known ones (non-equilibrium bounce-back of the
+// normal population plus a transverse momentum correction, D3Q19), so that
+// the cell carries the prescribed velocity (density from the known
+// populations) or the prescribed density (transverse velocity zero).
+// Cells whose entering links also touch a y or z wall keep the ghost values
+// pulled already.  f holds deviations f - w, times s (stored units) if RAW;
+// the lattice weights cancel in every difference used here.
+template <class St, bool RAW, int IN>
+__device__ __forceinline__ void zou_he_face(const Phys& p, int kind, float f[kQ]) {
+  // IN: c_x of the entering populations (+1 on the -x face, -1 on the +x face)
+  const float s = RAW ? St::kS : 1.0f, inv = RAW ? St::kInv : 1.0f;
+  float sz = 0.f, sout = 0.f, ny = 0.f, nz = 0.f;  // sums over c_x = 0 and leaving populations
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    if (cxq(i) == 0) {
+      sz += f[i];
+      ny += cyq(i) * f[i];
+      nz += czq(i) * f[i];
+    } else if (cxq(i) == -IN) {
+      sout += f[i];
+    }
+  }
+  const float known = 1.0f + (sz + 2.0f * sout) * inv;   // sum_Z f + 2 sum_out f
+  float rho, ux, uy, uz;
+  if (kind == BC_ZH_VELOCITY) {
+    ux = p.u_in[0]; uy = p.u_in[1]; uz = p.u_in[2];
+    rho = known / (1.0f - IN * ux);
+  } else {
+    rho = p.rho_out;
+    ux = IN * (1.0f - known / rho);
+    uy = 0.f; uz = 0.f;
+  }
+  const float Ny = 0.5f * ny - s * rho * uy * (1.0f / 3.0f);
+  const float Nz = 0.5f * nz - s * rho * uz * (1.0f / 3.0f);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    if (cxq(i) != IN) continue;
+    const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
+    f[i] = f[oppq(i)] + s * 6.0f * wq(i) * rho * cu - cyq(i) * Ny - czq(i) * Nz;
+  }
+}
+
+template <class St, bool RAW>
+__device__ __forceinline__ void zou_he(const Geo& g, const Phys& p, int x, int y, int z, float f[kQ]) {
+  const bool lo = x == 0 && g.bclo >= BC_ZH_VELOCITY;
+  const bool hi = x == g.nx - 1 && g.bchi >= BC_ZH_VELOCITY;
+  if (!lo && !hi) return;
+  if (!g.yper && (y == 0 || y == g.ny - 1)) return;
+  if (!g.zper && (z == 0 || z == g.nz - 1)) return;
+  if (lo)
+    zou_he_face<St, RAW, 1>(p, g.bclo, f);
+  else
+    zou_he_face<St, RAW, -1>(p, g.bchi, f);
 }
 
 // Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
@@ -216,10 +275,10 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
       continue;
     }
     float rg, ux, uy, uz;
-    if (kind == BC_VELOCITY) {
+    if (kind == BC_VELOCITY || kind == BC_ZH_VELOCITY) {
       rg = rho;
       ux = p.u_in[0]; uy = p.u_in[1]; uz = p.u_in[2];
-    } else {  // BC_PRESSURE
+    } else {  // BC_PRESSURE, BC_ZH_PRESSURE
       rg = p.rho_out;
       const float inv = 1.0f / rho;
       ux = jx * inv; uy = jy * inv; uz = jz * inv;

@@ -180,6 +180,7 @@ __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int
   for (int lx = lane; lx < w.bw; lx += 64) {
     float f[kQ];
     pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
+    zou_he<St, false>(a.g, a.p, w.x0 + lx, w.y0 + ly, z, f);
     float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {

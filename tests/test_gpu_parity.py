@@ -17,6 +17,7 @@ from tests.helpers import clap_fling, gpu_solver, l2rel, oracle_sim, plate
 pytestmark = pytest.mark.gpu
 
 P, Wl, V, PR = WL.PERIODIC, WL.WALL, WL.VELOCITY, WL.PRESSURE
+ZV, ZP = WL.ZH_VELOCITY, WL.ZH_PRESSURE
 
 
 def _say(*a):
@@ -44,6 +45,8 @@ LATTICE_CASES = [
     ("closed_box_all_walls", (33, 17, 9), [Wl] * 6, 0.8, {}),
     ("wall_x_periodic_yz", (36, 8, 8), [Wl, Wl, P, P, P, P], 0.75, dict(body_force=[0, 1e-5, 0])),
     ("z_walls", (64, 12, 10), [P, P, P, P, Wl, Wl], 0.66, {}),
+    ("zou_he_channel", (70, 18, 10), [ZV, ZP, Wl, Wl, P, P], 0.7, dict(u_in=[0.03, 0.005, 0.002])),
+    ("zou_he_periodic", (45, 12, 9), [ZV, ZP, P, P, P, P], 0.6, dict(u_in=[0.02, -0.004, 0.003], rho_out=1.01)),
 ]
 
 
@@ -234,6 +237,31 @@ def test_figure_eight_parity():
     fg = gpu.forces(t0, 80)
     fo = ora.forces()
     for k in (4, 5):
+        d = np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max()
+        print("coefficient", k, "max rel", d)
+        assert d <= 1e-3
+    gpu.close()
+
+
+def test_cylinder_zou_he_parity():
+    """Stationary circular cylinder (Sec. 3.1) behind a Zou-He velocity inlet
+    with a Zou-He pressure outlet and walls, 64x48x8, 150 steps: u and C_D
+    (and the lift of the off-centre start) against the oracle."""
+    _say("cylinder 64x48x8, d=8, Re 10, Zou-He faces, 150 steps, seed 4")
+    bx, wg, ph = WL.cylinder_case()
+    u0 = WL.velocity_noise((bx["nz"], bx["ny"], bx["nx"]), 4)
+    u0[0] += ph["u_inf"]
+    gpu = gpu_solver(bx, wg, ph, u0=u0)
+    ora = oracle_sim(bx, wg, ph, u0=u0)
+    gpu.step(150)
+    ora.run(150)
+    rho_o, u_o = ora.fields()
+    err = l2rel(gpu.fields("u"), u_o)
+    print("L2 rel u", err)
+    assert err <= 1e-5
+    fg = gpu.forces(0, 150)
+    fo = ora.forces()
+    for k in (4, 6):
         d = np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max()
         print("coefficient", k, "max rel", d)
         assert d <= 1e-3

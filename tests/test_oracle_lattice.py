@@ -201,3 +201,63 @@ def test_periodic_translation_invariance():
     a.run(5)
     b.run(5)
     np.testing.assert_allclose(np.roll(a.S, (1, 2), axis=(1, 3)), b.S, atol=1e-15)
+
+
+def _zh_state(seed, shape=(6, 7, 9)):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    u = 0.03 * rng.standard_normal((3,) + shape)
+    S = L.equilibrium(rho, u) + 1e-3 * rng.standard_normal((19,) + shape) * L.W[:, None, None, None]
+    return S
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_zou_he_faces_impose_velocity_and_density(walls):
+    """Zou-He faces (Sec. 3.1): after streaming, a velocity-face cell carries
+    exactly the prescribed velocity, a pressure-face cell exactly the
+    prescribed density with zero transverse momentum, and the normal
+    population obeys non-equilibrium bounce-back, f_n - f_n^eq equal for the
+    entering and the leaving one.  Cells whose entering links touch a wall
+    keep the equilibrium-ghost values."""
+    S = _zh_state(3)
+    yb = L.WALL if walls else L.PERIODIC
+    bc = [L.ZH_VELOCITY, L.ZH_PRESSURE, yb, yb, L.PERIODIC, L.PERIODIC]
+    u_in = np.array([0.04, -0.01, 0.015])
+    f = L.stream(S, bc, u_in, 1.02)
+    ys = slice(1, -1) if walls else slice(None)
+    rho, mom = L.moments(f)
+    # velocity face, x = 0
+    r0, m0 = rho[:, ys, 0], mom[:, :, ys, 0]
+    assert np.allclose(m0 / r0[None], u_in[:, None, None], rtol=0, atol=1e-14)
+    feq = L.equilibrium(r0, np.broadcast_to(u_in[:, None, None], (3,) + r0.shape))
+    assert np.allclose(f[1][:, ys, 0] - feq[1], f[2][:, ys, 0] - feq[2], rtol=0, atol=1e-15)
+    # pressure face, x = nx - 1
+    r1, m1 = rho[:, ys, -1], mom[:, :, ys, -1]
+    assert np.allclose(r1, 1.02, rtol=0, atol=1e-14)
+    assert np.allclose(m1[1:], 0.0, atol=1e-15)
+    u1 = m1 / r1[None]
+    feq = L.equilibrium(r1, u1)
+    assert np.allclose(f[2][:, ys, -1] - feq[2], f[1][:, ys, -1] - feq[1], rtol=0, atol=1e-15)
+    if walls:
+        g = L.stream(S, [L.VELOCITY, L.PRESSURE, yb, yb, L.PERIODIC, L.PERIODIC], u_in, 1.02)
+        for yy in (0, -1):
+            assert np.array_equal(f[:, :, yy, :], g[:, :, yy, :])
+    # nothing but the two faces changes
+    g = L.stream(S, [L.VELOCITY, L.PRESSURE, yb, yb, L.PERIODIC, L.PERIODIC], u_in, 1.02)
+    assert np.array_equal(f[:, :, :, 1:-1], g[:, :, :, 1:-1])
+
+
+def test_zou_he_uniform_flow_is_a_fixed_point():
+    """Uniform flow at the inlet velocity with rho = rho_out stays exactly
+    uniform through Zou-He inlet and outlet (periodic y, z)."""
+    shape = (4, 5, 8)
+    u_in = np.array([0.05, 0.0, 0.0])
+    u = np.broadcast_to(u_in[:, None, None, None], (3,) + shape).copy()
+    S = L.equilibrium(np.ones(shape), u)
+    bc = [L.ZH_VELOCITY, L.ZH_PRESSURE, L.PERIODIC, L.PERIODIC, L.PERIODIC, L.PERIODIC]
+    for _ in range(5):
+        f = L.stream(S, bc, u_in, 1.0)
+        rho, mom = L.moments(f)
+        S = L.collide(f, rho, mom / rho, np.zeros((3,) + shape), 0.8)
+    assert np.allclose(S, L.equilibrium(np.ones(shape), u), rtol=0, atol=1e-15)
