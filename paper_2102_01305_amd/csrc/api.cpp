@@ -128,7 +128,11 @@ void* next_state(ibmlbm_t h) { return h->ws + (h->cur_is_A ? h->L.fB.off : h->L.
 int validate_config(const ibmlbm_config* c, std::string& why) {
   char b[256];
   if (!c) { why = "null config"; return IBMLBM_EINVAL; }
-  if (c->nx < 4 || c->ny < 4 || c->nz < 4) { why = "nx, ny, nz must each be >= 4"; return IBMLBM_EINVAL; }
+  if (c->nx < 4 || c->ny < 4 || c->nz < 1) { why = "nx, ny must be >= 4 and nz >= 1"; return IBMLBM_EINVAL; }
+  // nz = 1 with a periodic span is the 2D scheme: D3Q19 on one periodic
+  // layer reduces exactly to D2Q9 (summing the populations that share
+  // (c_x, c_y) gives the D2Q9 weights, equilibrium, forcing and streaming)
+  if (c->nz < 4 && c->bc[4] != IBMLBM_BC_PERIODIC) { why = "nz < 4 needs a periodic z axis"; return IBMLBM_EINVAL; }
   if ((long long)c->nx * c->ny * c->nz > (1LL << 34)) { why = "box too large"; return IBMLBM_EINVAL; }
   for (int f = 0; f < 6; ++f) {
     if (c->bc[f] < 0 || c->bc[f] > 5) { snprintf(b, sizeof b, "bc[%d] unknown", f); why = b; return IBMLBM_EINVAL; }
@@ -278,18 +282,6 @@ double delta_h(double r) {
   return r <= 2.0 ? 0.25 * (1.0 + std::cos(0.5 * M_PI * r)) : 0.0;
 }
 
-// a(p, q) = sum_j delta(j - p) delta(j - q), periodic of length n if per
-double a1_h(double p, double q, int n, bool per) {
-  const double fb = std::floor(p) - 1.0;
-  double s = 0.0;
-  for (int k = 0; k < 4; ++k) {
-    double r = fb + k - q;
-    if (per) r -= n * std::rint(r / n);
-    s += delta_h(fb + k - p) * delta_h(r);
-  }
-  return s;
-}
-
 void pose_h(const ibmlbm_wing& w, double t, double& th, double& hx, double& hy) {
   double al = w.alpha_mean;
   if (w.alpha_shape == IBMLBM_ALPHA_SIN) {
@@ -393,8 +385,17 @@ double perimeter_conditioning(const std::vector<double>& xy, int n, const ibmlbm
 // cosine kernel makes the alternating mode exactly null; eigenvalues below
 // 1e-12 of the largest are dropped (minimum-norm solution).
 void span_pinv_row(int ns, std::vector<double>& G) {
-  std::vector<double> r(ns);
-  for (int j = 0; j < ns; ++j) r[j] = a1_h(0.5, j + 0.5, ns, true);
+  // kernel weights of a layer at z = 1/2 on the ns nodes of the periodic
+  // axis (support nodes that wrap onto one node add up, as they do for
+  // spans shorter than 4); r[j] = a(1/2, j + 1/2) = sum_i I(i) I(i - j)
+  std::vector<double> I(ns, 0.0);
+  for (int k = 0; k < 4; ++k) {
+    const int node = -1 + k;
+    I[((node % ns) + ns) % ns] += delta_h(node - 0.5);
+  }
+  std::vector<double> r(ns, 0.0);
+  for (int j = 0; j < ns; ++j)
+    for (int i = 0; i < ns; ++i) r[j] += I[i] * I[((i - j) % ns + ns) % ns];
   std::vector<double> lam(ns);
   double lmax = 0.0;
   for (int k = 0; k < ns; ++k) {

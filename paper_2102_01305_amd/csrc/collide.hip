@@ -74,6 +74,7 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
       for (int k = 0; k < 4; ++k) {
         int s = z - 2 + k;
         s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
+        s = s < 0 ? s + g.nz : s;                        // a span of one layer wraps twice
         const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
         dux += a.wz[k] * v.x;
         duy += a.wz[k] * v.y;

@@ -234,6 +234,7 @@ __device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, i
     for (int k = 0; k < 4; ++k) {
       int z = s - 1 + k;
       z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
+      z = z >= a.g.nz ? z - a.g.nz : z;                // a span of one layer wraps twice
       const float4 v = w.band[((long long)z * w.side + ly) * w.side + lx];
       h0 += a.wz[k] * (double)v.x;
       h1 += a.wz[k] * (double)v.y;

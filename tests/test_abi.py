@@ -130,3 +130,17 @@ def test_single_hip_runtime_after_load():
     import torch  # noqa: F401
     rts = L._hip_runtimes()
     assert len(rts) <= 1, rts
+
+
+def test_one_layer_span_is_accepted_only_periodic():
+    """nz = 1 with a periodic span is the 2D (D2Q9) scheme; short spans with
+    z walls are rejected."""
+    L, lib = _lib()
+    bx, wg = _plate()
+    one = dict(bx, nz=1)
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(one)), 0, None) > 0
+    from paper_2102_01305_amd.solver import make_wings
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(one)), 1, make_wings(wg)) > 0
+    walls = dict(bx, nz=2, bc=[WL.VELOCITY, WL.PRESSURE, WL.WALL, WL.WALL, WL.WALL, WL.WALL])
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(walls)), 0, None) == 0
+    assert b"periodic" in lib.ibmlbm_last_error(None)
