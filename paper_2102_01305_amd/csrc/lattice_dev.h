@@ -137,6 +137,31 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
   for (int i = 0; i < kQ; ++i) f[i] = RAW ? St::ldr(src[i]) : St::ld(src[i]);
 }
 
+// Global-memory view of a pointer.  Loads through it are global loads, which
+// the compiler knows cannot alias LDS; through a generic pointer each load
+// of a global-to-LDS copy would wait for the one before it.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+
+// Copy n values from global memory into LDS with four loads in flight per
+// thread.
+template <class T>
+__device__ __forceinline__ void copy_to_lds(T* dst, const T* src, int n) {
+  const auto* g = gmem(src);
+  const int bd = (int)blockDim.x;
+  int e = (int)threadIdx.x;
+  for (; e + 3 * bd < n; e += 4 * bd) {
+    const T v0 = g[e], v1 = g[e + bd], v2 = g[e + 2 * bd], v3 = g[e + 3 * bd];
+    dst[e] = v0;
+    dst[e + bd] = v1;
+    dst[e + 2 * bd] = v2;
+    dst[e + 3 * bd] = v3;
+  }
+  for (; e < n; e += bd) dst[e] = g[e];
+}
+
 // The solve a block of a grouped launch belongs to (binary search over the
 // block offsets, all in kernel arguments) and its block index within it.
 __device__ __forceinline__ int group_index(const Group& g, int& lb) {

@@ -225,8 +225,8 @@ __device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, i
   const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
   double* P = lds;                 // n * kPw
   double* H = P + n * kPw;         // cells * 4
-  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
-  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
+  copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
+  const auto* band = gmem(reinterpret_cast<const float*>(w.band));   // float4 records
   for (int c = threadIdx.x; c < cells; c += blockDim.x) {
     const int ly = c / w.bw, lx = c - ly * w.bw;
     double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
@@ -235,11 +235,11 @@ __device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, i
       int z = s - 1 + k;
       z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
       z = z >= a.g.nz ? z - a.g.nz : z;                // a span of one layer wraps twice
-      const float4 v = w.band[((long long)z * w.side + ly) * w.side + lx];
-      h0 += a.wz[k] * (double)v.x;
-      h1 += a.wz[k] * (double)v.y;
-      h2 += a.wz[k] * (double)v.z;
-      h3 += a.wz[k] * (double)v.w;
+      const long long o = 4 * (((long long)z * w.side + ly) * w.side + lx);
+      h0 += a.wz[k] * (double)band[o];
+      h1 += a.wz[k] * (double)band[o + 1];
+      h2 += a.wz[k] * (double)band[o + 2];
+      h3 += a.wz[k] * (double)band[o + 3];
     }
     H[4 * c] = h0;
     H[4 * c + 1] = h1;
@@ -308,13 +308,13 @@ __device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int
   double* G = lds;              // 2 * ns: G repeated so that G[d + ns] = G[d]
   double* Bc = G + 2 * ns;      // 3 * ns
   double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
+  const auto* Gg = gmem(a.G + w.g_off);
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const double g = a.G[w.g_off + i];
+    const double g = Gg[i];
     G[i] = g;
     G[i + ns] = g;
   }
-  const double* Bg = a.C + w.c_off + (size_t)p * 3 * ns;
-  for (int i = threadIdx.x; i < 3 * ns; i += blockDim.x) Bc[i] = Bg[i];
+  copy_to_lds(Bc, a.C + w.c_off + (size_t)p * 3 * ns, 3 * ns);
   __syncthreads();
   const int part = threadIdx.x / groups, t = threadIdx.x - part * groups;
   if (part < parts) {
@@ -378,12 +378,9 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
   double* Tl = P + n * kPw;                          // n * 3
   double* Y = Tl + 3 * n;                            // n * 3
   float* img = reinterpret_cast<float*>(Y + 3 * n);  // copies * cells * 3
-  const double* Mg = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
-  const double* Pg = a.pw + (size_t)a.slot * a.pw_step + w.pw_off;
-  const double* Tg = a.T + w.c_off + (size_t)s * n * 3;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) Mi[e] = Mg[e];
-  for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) P[e] = Pg[e];
-  for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) Tl[e] = Tg[e];
+  copy_to_lds(Mi, a.Minv + (size_t)a.slot * a.minv_step + w.minv_off, n * n);
+  copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
+  copy_to_lds(Tl, a.T + w.c_off + (size_t)s * n * 3, 3 * n);
   for (int i = threadIdx.x; i < copies * 3 * cells; i += blockDim.x) img[i] = 0.f;
   __syncthreads();
   for (int e = threadIdx.x; e < 3 * n; e += blockDim.x) {
