@@ -1,0 +1,93 @@
+"""Clap & fling over one full flapping period (two clap / fling events,
+Eq. 23 read as |sin|), 64x48x8 with c = 8 (T = 671 steps at f = 0.25):
+the lift and thrust histories of both foils against the FP64 oracle, for
+FP32, FP16 and BF16 storage and for the request served in a mixed batch.
+Bar: every step within 1e-3 of max|C| (FP32, FP16, served); BF16 is held
+to its own 3e-2 (its lift error is stated per step in the report line)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from tests.helpers import clap_fling, gpu_solver, oracle_sim
+
+pytestmark = pytest.mark.gpu
+
+CASE = dict(seed=6, nx=64, ny=48, nz=8, chord=8.0, re=100.0, j=0.5, f=0.25)
+_ORA = {}
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _steps():
+    from oracle import params
+    bx, wg, ph, u0 = clap_fling(**CASE)
+    return int(math.ceil(params.complete_case(bx, wg, ph)[1][0]["period_steps"]))
+
+
+def _oracle():
+    if "f" not in _ORA:
+        bx, wg, ph, u0 = clap_fling(**CASE)
+        ora = oracle_sim(bx, wg, ph, u0=u0)
+        ora.run(_steps())
+        _ORA["f"] = ora.forces()
+    return _ORA["f"]
+
+
+def _errors(fg, fo):
+    out = {}
+    for k, name in ((4, "cl"), (5, "ct")):
+        out[name] = max(np.abs(fg[:, w, k] - fo[:, w, k]).max() / np.abs(fo[:, w, k]).max()
+                        for w in range(fo.shape[1]))
+    return out
+
+
+BAR = {"fp32": 1e-3, "fp16": 1e-3, "bf16": 3e-2}
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
+def test_full_period(storage):
+    n = _steps()
+    _say("clap & fling 64x48x8, c=8, one period", n, "steps, storage", storage)
+    bx, wg, ph, u0 = clap_fling(**CASE)
+    gpu = gpu_solver(bx, wg, ph, u0=u0, storage=storage)
+    gpu.step(n)
+    fg = gpu.forces(0, n)
+    gpu.close()
+    e = _errors(fg, _oracle())
+    print(f"[period] {storage} max|dCL|/max|CL| {e['cl']:.3e} max|dCT|/max|CT| {e['ct']:.3e}", flush=True)
+    assert e["cl"] <= BAR[storage]
+    assert e["ct"] <= BAR[storage]
+
+
+def test_full_period_served():
+    """The same request served beside two others (a 64^3 and a 96x80x16
+    solve, admitted together) gives the oracle's history to the same bar."""
+    from paper_2102_01305_amd.serve import SweepRequest, SweepServer
+    from paper_2102_01305_amd.solver import complete_case
+
+    n = _steps()
+    _say("served clap & fling 64x48x8 with two others, one period")
+    reqs = []
+    others = [dict(seed=1, nx=64, ny=64, nz=64, chord=8.0, re=75.0, j=0.01, f=0.25),
+              dict(seed=2, nx=96, ny=80, nz=16, chord=10.0, re=150.0, j=2.0, f=0.25)]
+    for rid, c in enumerate([CASE] + others):
+        bx, wg, ph, u0 = clap_fling(**c)
+        gb, gw = complete_case(bx, wg, ph)
+        u = u0.copy()
+        u[0] += gb["u_in"][0]
+        reqs.append(SweepRequest(rid=rid, box=gb, wings=gw, steps=n if rid == 0 else 300 + 100 * rid,
+                                 arrival=0.0, u0=u))
+    srv = SweepServer(chunk=64)
+    res = srv.run(reqs)
+    assert all(r.error is None for r in res)
+    assert max(srv.batch_sizes) == 3
+    e = _errors(res[0].forces, _oracle())
+    print(f"[period] served max|dCL|/max|CL| {e['cl']:.3e} max|dCT|/max|CT| {e['ct']:.3e}", flush=True)
+    assert e["cl"] <= 1e-3
+    assert e["ct"] <= 1e-3
