@@ -83,6 +83,26 @@ def measured_traffic(name, storage):
         return None
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Bandwidth of a plain device copy (read + write of nbytes), timed with
+    events on the stream the copy runs on."""
+    import torch
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    gbs = 2.0 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def copy_calibration(nbytes=1 << 30, reps=5):
     """A plain device copy of known size, for scaling the HBM byte counters:
     each launch reads and writes `nbytes`."""
@@ -243,6 +263,7 @@ def main():
     cells_per_launch = tim["collide_cells"] / nl if nl else float("nan")
     achieved = bpc * cells_per_launch / (k6_ms * 1e-3) / 1e9 if nl else float("nan")
     traffic = measured_traffic(name, args.storage)
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -264,7 +285,8 @@ def main():
                      "kernel": "k_collide", "kernel_ms": round(k6_ms, 5),
                      "bytes_per_cell": bpc, "cells_per_launch": cells_per_launch,
                      "timed_launches": tim["collide_launches"],
-                     "marker_ms_per_step": round(tim["marker_ms"] / max(tim["collide_launches"], 1), 5)},
+                     "marker_ms_per_step": round(tim["marker_ms"] / max(tim["collide_launches"], 1), 5),
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "hbm_frac_whole_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
     }
     if not args.no_serve:
