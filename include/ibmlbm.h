@@ -3,7 +3,12 @@
  * solver: D3Q19 BGK with Guo forcing (Sec. 2.1, Eqs. 1-9) coupled to the
  * implicit velocity-correction immersed boundary method (Sec. 2.2,
  * Eqs. 10-19) on rigid elliptic foils in clap & fling motion (Sec. 3.3,
- * Eqs. 23-24), with force integration over the markers (Sec. 3.7, Eq. 26).
+ * Eqs. 23-24) or on the figure-eight stroke (Sec. 3.2, Eqs. 20-22), with
+ * force integration over the markers (Sec. 3.7, Eq. 26).  Faces take
+ * periodic, bounce-back wall, equilibrium or Zou-He inflow/outflow rules
+ * (Sec. 2.1, Sec. 3.1).  nz = 1 with a periodic span is the paper's 2D
+ * D2Q9 scheme exactly (summing the D3Q19 populations of equal (c_x, c_y)
+ * gives the D2Q9 weights of Eq. 5, equilibrium, forcing and streaming).
  *
  * Conventions (all calls):
  *  - Lattice units, dx = dt = 1.  The box has nx*ny*nz cells; host arrays are

@@ -49,7 +49,7 @@ struct WingGeom {
   int side = 0;                    // pitch of the per-layer node-box images
 };
 
-constexpr int kPwStride = 14;      // doubles per perimeter record (kernels.hip)
+constexpr int kPwStride = 14;      // doubles per perimeter record (markers.hip)
 
 struct MarkerLayout {
   Region ref, G, Minv, pw, C, T, X, U, B, rhoB, duB, fpart, hist;

@@ -1,5 +1,5 @@
 // Internal declarations shared by the host API (api.cpp) and the gfx950
-// kernels (kernels.hip).  Not part of the public ABI.
+// kernels (collide.hip, markers.hip).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
