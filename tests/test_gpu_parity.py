@@ -161,12 +161,10 @@ def test_resume_with_markers_matches():
     b.step(12)
     b.init_fields(fdist=b.fields("fdist"), step0=12)
     b.step(18)
-    assert l2rel(b.fields("u"), a.fields("u")) <= 1e-6
-    # spreading adds with float atomics, so the two runs differ in the last
-    # bits; compare each force/moment column against its own scale
-    fa, fb = a.forces(12, 18), b.forces(12, 18)
-    scale = np.abs(fa[:, :, :4]).max()
-    assert np.abs(fb[:, :, :4] - fa[:, :, :4]).max() <= 1e-5 * scale
+    # every reduction is in a fixed order and the FP64 read-back of f
+    # round-trips exactly, so the resumed run is the same bit for bit
+    np.testing.assert_array_equal(b.fields("fdist"), a.fields("fdist"))
+    np.testing.assert_array_equal(b.forces(12, 18), a.forces(12, 18))
     a.close()
     b.close()
 
