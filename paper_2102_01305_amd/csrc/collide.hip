@@ -160,7 +160,7 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   T* __restrict__ D = static_cast<T*>(dst);
   if (IBM && lb == 0) reduce_forces(a);
   // Waves to (64-cell chunk, row).  FP32: a block is one chunk of 4
-  // consecutive rows.  16-bit storage: waves run along x first, so the
+  // consecutive rows (tiles in XCD runs, below).  16-bit storage: waves run along x first, so the
   // chunks of a row sit in one block and the cache line each chunk shares
   // with its neighbour (the x -/+ 1 pulls) is fetched from memory once; at
   // 2 bytes a wave reads a single line per population row, so these shared
@@ -171,8 +171,20 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
     xc = gw % a.nxc;
     row = gw / a.nxc;
   } else {
-    xc = lb % a.nxc;
-    row = (lb / a.nxc) * kBlockRows + (int)threadIdx.y;
+    // Workgroups are dealt to the 8 XCDs in turn; a single solve's tiles are
+    // reordered so that each XCD takes runs of 4 block rows (all chunks of
+    // 16 lattice rows), and the cache lines two chunks of a row share are
+    // fetched by one L2.  Bijective on the tiles; grouped launches keep the
+    // plain order.
+    int lt = lb;
+    const int G = 4 * a.nxc;
+    const int M = (int)(gridDim.x / (8 * G)) * 8 * G;
+    if (lt < M && (int)gridDim.x == a.nblocks) {
+      const int xcd = lt & 7, k = lt >> 3;
+      lt = ((k / G) * 8 + xcd) * G + k % G;
+    }
+    xc = lt % a.nxc;
+    row = (lt / a.nxc) * kBlockRows + (int)threadIdx.y;
   }
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
