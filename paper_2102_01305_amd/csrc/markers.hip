@@ -227,24 +227,42 @@ __device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, i
   double* H = P + n * kPw;         // cells * 4
   copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
   const auto* band = gmem(reinterpret_cast<const float*>(w.band));   // float4 records
-  for (int c = threadIdx.x; c < cells; c += blockDim.x) {
-    const int ly = c / w.bw, lx = c - ly * w.bw;
-    double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+  long long lay[4];                                  // the 4 layers of the span support
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      int z = s - 1 + k;
-      z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
-      z = z >= a.g.nz ? z - a.g.nz : z;                // a span of one layer wraps twice
-      const long long o = 4 * (((long long)z * w.side + ly) * w.side + lx);
-      h0 += a.wz[k] * (double)band[o];
-      h1 += a.wz[k] * (double)band[o + 1];
-      h2 += a.wz[k] * (double)band[o + 2];
-      h3 += a.wz[k] * (double)band[o + 3];
+  for (int k = 0; k < 4; ++k) {
+    int z = s - 1 + k;
+    z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
+    z = z >= a.g.nz ? z - a.g.nz : z;                // a span of one layer wraps twice
+    lay[k] = (long long)z * w.side * w.side;
+  }
+  const int bd = (int)blockDim.x;
+  for (int c0 = threadIdx.x; c0 < cells; c0 += 3 * bd) {
+    // up to three cells per thread: all 12 records in flight before the sums
+    float v[3][4][4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int c = c0 + j * bd;
+      const int cc = c < cells ? c : c0;
+      const int ly = cc / w.bw, lx = cc - ly * w.bw;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const long long o = 4 * (lay[k] + (long long)ly * w.side + lx);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[j][k][q] = band[o + q];
+      }
     }
-    H[4 * c] = h0;
-    H[4 * c + 1] = h1;
-    H[4 * c + 2] = h2;
-    H[4 * c + 3] = h3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int c = c0 + j * bd;
+      if (c >= cells) break;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double h = 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) h += a.wz[k] * (double)v[j][k][q];
+        H[4 * c + q] = h;
+      }
+    }
   }
   __syncthreads();
   double th, thd, hx, hy, vx, vy;
@@ -378,6 +396,9 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
   double* Tl = P + n * kPw;                          // n * 3
   double* Y = Tl + 3 * n;                            // n * 3
   float* img = reinterpret_cast<float*>(Y + 3 * n);  // copies * cells * 3
+  // rho_B of this thread's first marker, fetched while the block loads
+  const int p0 = (int)threadIdx.x;
+  const double rho_p0 = p0 < n ? gmem(a.rhoB)[(size_t)w.moff + (size_t)p0 * ns + s] : 0.0;
   copy_to_lds(Mi, a.Minv + (size_t)a.slot * a.minv_step + w.minv_off, n * n);
   copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
   copy_to_lds(Tl, a.T + w.c_off + (size_t)s * n * 3, 3 * n);
@@ -404,7 +425,7 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
     a.duB[3 * m] = y0 / w.dA;
     a.duB[3 * m + 1] = y1 / w.dA;
     a.duB[3 * m + 2] = y2 / w.dA;
-    const double r = a.rhoB[m];
+    const double r = p == p0 ? rho_p0 : a.rhoB[m];
     const double bx = -2.0 * r * y0, by = -2.0 * r * y1, bz = -2.0 * r * y2;   // on the body
     fx += bx;
     fy += by;
