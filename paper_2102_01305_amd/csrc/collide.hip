@@ -41,14 +41,8 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   float f[kQ];
   pull19<St, true>(S, g, x, y, z, f);
   if (ZH) zou_he<St, true>(g, a.p, x, y, z, f);
-  float dr = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;   // kS drho, kS j
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    dr += f[i];
-    jx += cxq(i) * f[i];
-    jy += cyq(i) * f[i];
-    jz += czq(i) * f[i];
-  }
+  float dr, jx, jy, jz;                            // kS drho, kS j
+  moments19(f, dr, jx, jy, jz);
   const float drho = dr * kInv;
   const float rho = 1.0f + drho;
   const float srho = kS * rho;
@@ -67,6 +61,7 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
     bool hit = false;
     for (int w = 0; w < a.nw; ++w) {
       const FoilBox& b = a.box[w];
+      if (y < b.y0 || y >= b.y0 + b.h) continue;         // wave-uniform: most rows miss
       if (!in_box(b, x, y)) continue;
       const int lx = x - b.x0, ly = y - b.y0;
       hit = true;
@@ -99,14 +94,26 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
     const float uF = ux * Fx + uy * Fy + uz * Fz;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-      const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
-      const float cF = cxq(i) * Fx + cyq(i) * Fy + czq(i) * Fz;
+      const float cu = cdot(i, ux, uy, uz);
+      const float cF = cdot(i, Fx, Fy, Fz);
       o[i] += k * wq(i) * (3.0f * (cF - uF) + 9.0f * cu * cF);   // Eq. 8
     }
   }
   T* own = D + rowbase(g, y, z);
+  if constexpr (sizeof(T) == 2) {
+    // 16-bit storage: one buffer descriptor over the cell row's 19
+    // population rows, so each store takes its row as a scalar offset and
+    // the lane's x as the vector offset, with no per-store address
+    // arithmetic (FP32 measured faster with plain stores)
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(own, 0, (int)(kQ * g.ps * (long long)sizeof(T)), kRawBufferWord3);
+    const int bo = x * (int)sizeof(T);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) St::stnr(own + (long long)i * g.ps + x, o[i]);
+    for (int i = 0; i < kQ; ++i) St::stb(rs, bo, (int)(i * g.ps * (long long)sizeof(T)), o[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) St::stnr(own + (long long)i * g.ps + x, o[i]);
+  }
   if (x == 0 || x == g.nx - 1) {
 #pragma unroll
     for (int i = 0; i < kQ; ++i) o[i] *= kInv;
@@ -167,7 +174,7 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   // lines are a large part of its reads.
   int xc, row;
   if (sizeof(T) == 2) {
-    const int gw = lb * kBlockRows + (int)threadIdx.y;
+    const int gw = __builtin_amdgcn_readfirstlane(lb * kBlockRows + (int)threadIdx.y);
     xc = gw % a.nxc;
     row = gw / a.nxc;
   } else {

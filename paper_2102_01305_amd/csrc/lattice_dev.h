@@ -38,7 +38,10 @@ __host__ __device__ constexpr double wqd(int i) {
 // ld()/st() take and give f~ itself; ldr()/stnr() the stored value, which is
 // kS f~ (kS = 2^12 for FP16, else 1), for the collide kernel, which works
 // in those units throughout.  stn/stnr are streaming (non-temporal) stores
-// for data the current kernel will not read again.
+// for data the current kernel will not read again; stb is stnr through a
+// buffer descriptor (byte offsets: vo per lane, so from a scalar register).
+constexpr int kRawBufferWord3 = 0x00020000;   // untyped (raw) buffer, 32-bit data format
+constexpr int kStreamAux = 2;                 // non-temporal
 struct StF32 {
   using T = float;
   static constexpr float kS = 1.0f, kInv = 1.0f;
@@ -47,6 +50,9 @@ struct StF32 {
   __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(v, p); }
   __device__ static float ldr(const T* p) { return *p; }
   __device__ static void stnr(T* p, float v) { __builtin_nontemporal_store(v, p); }
+  __device__ static void stb(__amdgpu_buffer_rsrc_t r, int vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, so, kStreamAux);
+  }
 };
 struct StF16 {
   using T = __half;
@@ -58,6 +64,9 @@ struct StF16 {
   __device__ static float ld(const T* p) { return ldr(p) * kInv; }
   __device__ static void st(T* p, float v) { *p = __float2half_rn(v * kS); }
   __device__ static void stn(T* p, float v) { stnr(p, v * kS); }
+  __device__ static void stb(__amdgpu_buffer_rsrc_t r, int vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, vo, so, kStreamAux);
+  }
 };
 struct StBF16 {
   using T = unsigned short;
@@ -69,6 +78,9 @@ struct StBF16 {
   __device__ static void stn(T* p, float v) { __builtin_nontemporal_store(enc(v), p); }
   __device__ static float ldr(const T* p) { return ld(p); }
   __device__ static void stnr(T* p, float v) { stn(p, v); }
+  __device__ static void stb(__amdgpu_buffer_rsrc_t r, int vo, int so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b16(enc(v), r, vo, so, kStreamAux);
+  }
 };
 
 // Row-major slabs: the 19 populations of one lattice row are adjacent, so a
@@ -248,28 +260,66 @@ __device__ __forceinline__ void zou_he(const Geo& g, const Phys& p, int x, int y
     zou_he_face<St, RAW, -1>(p, g.bchi, f);
 }
 
+// c_i . v summed over the nonzero components of c_i in x, y, z order.  A
+// product 0 * v is not folded away under IEEE rules (v could be infinite),
+// and leaving it out changes no finite result.
+__device__ __forceinline__ float cdot(int i, float vx, float vy, float vz) {
+  const int c[3] = {cxq(i), cyq(i), czq(i)};
+  const float v[3] = {vx, vy, vz};
+  float r = 0.f;
+  bool any = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] == 0) continue;
+    const float t = c[d] > 0 ? v[d] : -v[d];
+    r = any ? r + t : t;
+    any = true;
+  }
+  return r;
+}
+
+// Zeroth and first moments of 19 values: sum f_i and sum c_i f_i, in i order
+// (zero components of c_i left out, as in cdot).
+__device__ __forceinline__ void moments19(const float f[kQ], float& d, float& jx, float& jy, float& jz) {
+  d = jx = jy = jz = 0.f;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    d += f[i];
+    if (cxq(i) != 0) jx = cxq(i) > 0 ? jx + f[i] : jx - f[i];
+    if (cyq(i) != 0) jy = cyq(i) > 0 ? jy + f[i] : jy - f[i];
+    if (czq(i) != 0) jz = czq(i) > 0 ? jz + f[i] : jz - f[i];
+  }
+}
+
 // Equilibrium deviation f~eq_i = w_i (drho + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
 __device__ __forceinline__ float feq_dev(int i, float drho, float rho, float ux, float uy,
                                          float uz, float usq) {
-  const float cu = cxq(i) * ux + cyq(i) * uy + czq(i) * uz;
+  const float cu = cdot(i, ux, uy, uz);
+  return wq(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
+}
+
+// feq_dev with every operation rounded on its own (no contraction into
+// FMAs), so that it gives the same bits in every kernel it is compiled into.
+__device__ __forceinline__ float feq_dev_strict(int i, float drho, float rho, float ux, float uy,
+                                                float uz, float usq) {
+#pragma clang fp contract(off)
+  const float cu = cdot(i, ux, uy, uz);
   return wq(i) * (drho + rho * (3.0f * cu + 4.5f * cu * cu - 1.5f * usq));
 }
 
 // Ghost records of the state being written, from the post-collision values
 // `o` of a boundary cell (x == 0 or x == nx-1).  The ghost at (-1, y', z')
 // for population i (c_x = +1) is read only by cell (0, y'+c_y, z'+c_z); the
-// +x ghost likewise for c_x = -1.
+// +x ghost likewise for c_x = -1.  This runs inside the collide and, after an
+// initialisation, in the ghost kernel; a resumed run has to find the same
+// ghosts as an uninterrupted one, so the arithmetic is kept free of
+// contraction and gives the same bits in both.
 template <class St>
 __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const Phys& p,
                              int x, int y, int z, const float o[kQ]) {
-  float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    drho += o[i];
-    jx += cxq(i) * o[i];
-    jy += cyq(i) * o[i];
-    jz += czq(i) * o[i];
-  }
+#pragma clang fp contract(off)
+  float drho, jx, jy, jz;
+  moments19(o, drho, jx, jy, jz);
   const float rho = 1.0f + drho;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
@@ -312,7 +362,7 @@ __device__ void write_ghosts(typename St::T* __restrict__ D, const Geo& g, const
 #pragma unroll
     for (int i = 0; i < kQ; ++i)
       if (cxq(i) == dir)
-        St::st(ghost_ptr(D, g, side, y, z, i), feq_dev(i, rg - 1.0f, rg, ux, uy, uz, usq));
+        St::st(ghost_ptr(D, g, side, y, z, i), feq_dev_strict(i, rg - 1.0f, rg, ux, uy, uz, usq));
   }
 }
 
