@@ -86,9 +86,25 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   }
   const float usq = ux * ux + uy * uy + uz * uz;
   const float om = a.p.omega;
+  // Equilibrium (Eq. 4) by opposite pairs: with cu_opp = -cu, the even part
+  // w (drho + rho (4.5 cu^2 - 1.5 u^2)) is shared and the odd part 3 w rho cu
+  // changes sign, so each pair costs one evaluation
+  const float c15 = 1.5f * usq;
+  const float k1[2] = {wq(1) * srho, wq(7) * srho}, k3[2] = {3.0f * wq(1) * srho, 3.0f * wq(7) * srho},
+              kd[2] = {wq(1) * dr, wq(7) * dr};
   float o[kQ];
+  o[0] = f[0] - om * (f[0] - (wq(0) * dr - wq(0) * srho * c15));
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) o[i] = f[i] - om * (f[i] - feq_dev(i, dr, srho, ux, uy, uz, usq));
+  for (int i = 1; i < kQ; ++i) {
+    if (oppq(i) < i) continue;
+    const int c = i < 7 ? 0 : 1;                       // axis or diagonal weight
+    const float cu = cdot(i, ux, uy, uz);
+    const float A = k1[c] * (4.5f * cu * cu - c15) + kd[c];
+    const float B = k3[c] * cu;
+    const float fp = A + B, fm = A - B;                // feq of i and of opp(i)
+    o[i] = f[i] - om * (f[i] - fp);
+    o[oppq(i)] = f[oppq(i)] - om * (f[oppq(i)] - fm);
+  }
   if (forced) {
     const float k = a.p.guo_k;
     const float uF = ux * Fx + uy * Fy + uz * Fz;
