@@ -52,7 +52,7 @@ struct WingGeom {
 constexpr int kPwStride = 14;      // doubles per perimeter record (markers.hip)
 
 struct MarkerLayout {
-  Region ref, G, Minv, pw, C, T, X, U, B, rhoB, duB, fpart, hist;
+  Region ref, G, Minv, pw, T, X, U, B, rhoB, duB, fpart, hist;
   std::vector<Region> band, corr;
   size_t end = 0;
   int m_total = 0, layers = 0, perims = 0;
@@ -425,6 +425,15 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
     why = "foils are extruded over the span: z must be periodic";
     return IBMLBM_EINVAL;
   }
+  if (nw > 0 && marker_span_lds(c.nz) > kMaxLds) {
+    int top = c.nz;
+    while (top > 1 && marker_span_lds(top) > kMaxLds) --top;
+    char b[160];
+    snprintf(b, sizeof b, "a span of %d layers does not fit the marker kernels' local memory (at most %d)",
+             c.nz, top);
+    why = b;
+    return IBMLBM_EINVAL;
+  }
   for (int k = 0; k < nw; ++k) {
     const ibmlbm_wing& x = w[k];
     if (x.sense != 1.0 && x.sense != -1.0) { why = "sense must be +1 or -1"; return IBMLBM_EINVAL; }
@@ -509,7 +518,6 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
   take(M.pw, (size_t)kFactorWindow * M.perims * kPwStride * 8);
   M.minv_step = (int)nMinv;
   M.pw_step = M.perims * kPwStride;
-  take(M.C, 3 * m * 8);
   take(M.T, 3 * m * 8);
   take(M.X, 3 * m * 8);
   take(M.U, 3 * m * 8);
@@ -615,7 +623,6 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ma.rhoB = at<double>(h, h->M.rhoB);
   ma.duB = at<double>(h, h->M.duB);
   ma.pw = at<double>(h, h->M.pw);
-  ma.C = at<double>(h, h->M.C);
   ma.T = at<double>(h, h->M.T);
   ma.fpart = at<double>(h, h->M.fpart);
   ca.fpart = ma.fpart;

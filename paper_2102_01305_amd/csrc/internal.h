@@ -86,7 +86,7 @@ struct WingDev {
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
   int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
-  int c_off;                 // offset of this foil's intermediates B, T (np x 3 x ns)
+  int c_off;                 // offset of this foil's span-solved T (ns x np x 3)
   int layer_off;             // offset of this foil's layers in the force partials
   int shape;
   double hinge0[2], theta0, sense, mean, amp, period, phase, tamp, tang;
@@ -114,7 +114,6 @@ struct MarkerArgs {
   long long win_t0;          // first step of the precomputed window
   int slot;                  // this step's slot in the window
   int pw_step, minv_step;    // doubles per slot
-  double* C;                 // B column-major: [marker p][component][layer]
   double* T;                 // span-solved B, layer-major: [layer][marker p][component]
   double* fpart;             // [layer]: Fx, Fy, Fz, Mz of each span layer
   double* X;                 // 3 per marker
@@ -152,5 +151,9 @@ hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, 
                          hipStream_t s);
 hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void* const* dev, int n,
                           hipStream_t s);
+// LDS bytes of the per-marker interpolation and span-solve block for a span
+// of ns layers (markers.hip), against the device's kMaxLds per block.
+size_t marker_span_lds(int ns);
+constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace ibmk

@@ -3,9 +3,9 @@
 //  factor    marker kinematics (Eqs. 20-23), the perimeter block of the
 //            no-slip matrix and its inverse (Eq. 18), for a window of steps.
 //  band      rho, u* over the node box of each foil (Eqs. 2, 11).
-//  interp    delta interpolation of rho and u* to the markers (Eqs. 14, 17),
-//            B = U_B - I u* (Eq. 19).
-//  span      the span part of the minimum-norm solve (Eq. 19).
+//  interp_span  per marker, on every span layer: delta interpolation of rho
+//            and u* (Eqs. 14, 17), B = U_B - I u* (Eq. 19), and the span part
+//            of the minimum-norm solve (Eq. 19).
 //  layer     the perimeter part of the solve, du_B, the force and moment of
 //            each layer (Eq. 26) and sum_l du_B D dA over the layer (Eq. 15).
 #include "lattice_dev.h"
@@ -211,107 +211,43 @@ __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, in
   return blk;
 }
 
-// Block (foil, span layer s): delta interpolation of rho and u* to the
-// layer's markers (Eq. 17) and B = U_B - I u* (Eq. 19), in FP64.  The span
-// factor of D is applied first: H(x, y) = sum_k wz_k band(x, y, s - 1 + k)
-// over the foil's box, kept in LDS; then one thread per marker sums its
-// 4 x 4 xy nodes.  B is also written column-major (marker, component, layer)
-// for the span solve.
-__device__ __forceinline__ void interp_block(const MarkerArgs& __restrict__ a, int lb) {
-  extern __shared__ double lds[];
-  int wi;
-  const int s = find_layer_block(a, lb, wi);
-  const WingDev& w = a.w[wi];
-  const int n = w.np, ns = w.ns, cells = w.bw * w.bh;
-  double* P = lds;                 // n * kPw
-  double* H = P + n * kPw;         // cells * 4
-  copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
-  const auto* band = gmem(reinterpret_cast<const float*>(w.band));   // float4 records
-  long long lay[4];                                  // the 4 layers of the span support
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int z = s - 1 + k;
-    z = z < 0 ? z + a.g.nz : (z >= a.g.nz ? z - a.g.nz : z);
-    z = z >= a.g.nz ? z - a.g.nz : z;                // a span of one layer wraps twice
-    lay[k] = (long long)z * w.side * w.side;
-  }
-  const int bd = (int)blockDim.x;
-  for (int c0 = threadIdx.x; c0 < cells; c0 += 3 * bd) {
-    // up to three cells per thread: all 12 records in flight before the sums
-    float v[3][4][4];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int c = c0 + j * bd;
-      const int cc = c < cells ? c : c0;
-      const int ly = cc / w.bw, lx = cc - ly * w.bw;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const long long o = 4 * (lay[k] + (long long)ly * w.side + lx);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[j][k][q] = band[o + q];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int c = c0 + j * bd;
-      if (c >= cells) break;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        double h = 0.0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) h += a.wz[k] * (double)v[j][k][q];
-        H[4 * c + q] = h;
-      }
-    }
-  }
-  __syncthreads();
-  double th, thd, hx, hy, vx, vy;
-  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
-  for (int p = threadIdx.x; p < n; p += blockDim.x) {
-    const double* r = P + p * kPw;
-    const int bx = (int)r[12] - w.x0, by = (int)r[13] - w.y0;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-    for (int oy = 0; oy < 4; ++oy) {
-#pragma unroll
-      for (int ox = 0; ox < 4; ++ox) {
-        const double D = r[4 + ox] * r[8 + oy];
-        const double* h = H + 4 * ((by + oy) * w.bw + bx + ox);
-        s0 += D * h[0];
-        s1 += D * h[1];
-        s2 += D * h[2];
-        s3 += D * h[3];
-      }
-    }
-    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
-    const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
-    a.X[3 * m] = r[0];
-    a.X[3 * m + 1] = r[1];
-    a.X[3 * m + 2] = s + 0.5;
-    a.U[3 * m] = Ux;
-    a.U[3 * m + 1] = Uy;
-    a.U[3 * m + 2] = 0.0;
-    a.rhoB[m] = s0;
-    const double b[3] = {Ux - s1, Uy - s2, 0.0 - s3};   // Eq. 19: B = U_B - I u*
-    for (int c = 0; c < 3; ++c) {
-      a.B[3 * m + c] = b[c];
-      a.C[w.c_off + ((size_t)p * 3 + c) * ns + s] = b[c];
-    }
-  }
+// Block (foil, perimeter marker p): the marker's delta interpolation on
+// every span layer and the span part of the minimum-norm solve.
+//  * The band records of the marker's 4 x 4 xy support nodes on every layer
+//    are read once into LDS.  D = D_xy wz factors, so per layer z the xy sum
+//    R(z) = sum_nodes D_xy band(node, z) is made once (FP64), and rho_B and
+//    I u* at the marker on layer s are sum_k wz_k R(s - 1 + k), k = 0..3
+//    (Eq. 17); B = U_B - I u* (Eq. 19).
+//  * T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
+//    row of the circulant span factor: each thread makes four consecutive
+//    outputs from a sliding window of G over one part of the s2 range; the
+//    parts are added in a fixed order.  T is written layer-major.
+// One block holds every layer of its marker, so B never leaves the block.
+__host__ __device__ inline int span_parts(int ns, int threads) {
+  const int groups = (ns + 3) / 4;                   // threads per part
+  const int parts = threads / groups;
+  return parts < 1 ? 1 : (parts > 8 ? 8 : parts);
 }
 
-__global__ void __launch_bounds__(256) k_interp(Group gr) {
-  int lb;
-  const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
-  interp_block(*a, lb);
+// Threads of an interp_span block: 512 (more parts of the span range in
+// parallel) where its LDS fits, else 256.
+__host__ __device__ inline size_t interp_span_lds(int ns, int threads);
+__host__ __device__ inline int span_threads(int ns) {
+  return interp_span_lds(ns, 512) <= 150 * 1024 ? 512 : 256;
 }
 
-// Block (foil, perimeter marker p): the span part of the minimum-norm solve,
-// T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
-// row of the circulant span factor.  Each thread makes four consecutive
-// outputs from a sliding window of G over one part of the s2 range; the
-// parts are added in a fixed order.  T is written layer-major.
-__device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int lb) {
+// LDS of a block: G (2 ns), B (3 ns), partial sums (parts x 3 ns), the xy
+// sums R (4 ns), the marker's record, then the band records (16 ns float4,
+// 16-byte aligned).
+__host__ __device__ inline size_t interp_span_doubles(int ns, int parts) {
+  const size_t d = (size_t)(9 + 3 * parts) * ns + kPw;
+  return (d + 1) / 2 * 2;
+}
+__host__ __device__ inline size_t interp_span_lds(int ns, int threads) {
+  return interp_span_doubles(ns, span_parts(ns, threads)) * sizeof(double) + 16 * (size_t)ns * 16;
+}
+
+__device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
   int wi = 0, p = lb;
   while (wi + 1 < a.nw && p >= a.w[wi].np) {
@@ -320,19 +256,84 @@ __device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int
   }
   const WingDev& w = a.w[wi];
   const int ns = w.ns, n = w.np;
-  const int groups = (ns + 3) / 4;                   // threads per part
-  int parts = (int)blockDim.x / groups;
-  parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
+  const int groups = (ns + 3) / 4;
+  const int parts = span_parts(ns, (int)blockDim.x);
+  const int bd = (int)blockDim.x;
   double* G = lds;              // 2 * ns: G repeated so that G[d + ns] = G[d]
   double* Bc = G + 2 * ns;      // 3 * ns
   double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
+  double* R = Pa + (size_t)parts * 3 * ns;                              // 4 * ns
+  double* r = R + 4 * ns;                                               // kPw
+  float4* rec = reinterpret_cast<float4*>(lds + interp_span_doubles(ns, parts));  // [node][layer]
   const auto* Gg = gmem(a.G + w.g_off);
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+  for (int i = threadIdx.x; i < ns; i += bd) {
     const double g = Gg[i];
     G[i] = g;
     G[i + ns] = g;
   }
-  copy_to_lds(Bc, a.C + w.c_off + (size_t)p * 3 * ns, 3 * ns);
+  copy_to_lds(r, a.pw + (size_t)a.slot * a.pw_step + w.pw_off + (size_t)p * kPw, kPw);
+  __syncthreads();
+  {
+    const int bx = (int)r[12] - w.x0, by = (int)r[13] - w.y0;
+    typedef float v4f __attribute__((ext_vector_type(4)));   // one 16-byte load per record
+    const auto* band = gmem(reinterpret_cast<const v4f*>(w.band));
+    for (int e = threadIdx.x; e < 16 * ns; e += bd) {
+      const int node = e / ns, z = e - node * ns;
+      const v4f v = band[((long long)z * w.side + by + (node >> 2)) * w.side + bx + (node & 3)];
+      rec[e] = make_float4(v.x, v.y, v.z, v.w);
+    }
+  }
+  __syncthreads();
+  double th, thd, hx, hy, vx, vy;
+  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
+  for (int z = threadIdx.x; z < ns; z += bd) {
+    double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) {
+#pragma unroll
+      for (int ox = 0; ox < 4; ++ox) {
+        const float4 v = rec[(size_t)(oy * 4 + ox) * ns + z];
+        const double D = r[4 + ox] * r[8 + oy];
+        R0 += D * (double)v.x;
+        R1 += D * (double)v.y;
+        R2 += D * (double)v.z;
+        R3 += D * (double)v.w;
+      }
+    }
+    R[4 * z] = R0;
+    R[4 * z + 1] = R1;
+    R[4 * z + 2] = R2;
+    R[4 * z + 3] = R3;
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < ns; s += bd) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int z = s - 1 + k;                             // the 4 layers of the span support
+      z = z < 0 ? z + ns : (z >= ns ? z - ns : z);
+      z = z >= ns ? z - ns : z;                      // a span of one layer wraps twice
+      s0 += a.wz[k] * R[4 * z];
+      s1 += a.wz[k] * R[4 * z + 1];
+      s2 += a.wz[k] * R[4 * z + 2];
+      s3 += a.wz[k] * R[4 * z + 3];
+    }
+    const size_t m = (size_t)w.moff + (size_t)p * ns + s;
+    a.X[3 * m] = r[0];
+    a.X[3 * m + 1] = r[1];
+    a.X[3 * m + 2] = s + 0.5;
+    a.U[3 * m] = Ux;
+    a.U[3 * m + 1] = Uy;
+    a.U[3 * m + 2] = 0.0;
+    a.rhoB[m] = s0;
+    const double b[3] = {Ux - s1, Uy - s2, 0.0 - s3};   // Eq. 19: B = U_B - I u*
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.B[3 * m + c] = b[c];
+      Bc[c * ns + s] = b[c];
+    }
+  }
   __syncthreads();
   const int part = threadIdx.x / groups, t = threadIdx.x - part * groups;
   if (part < parts) {
@@ -362,7 +363,7 @@ __device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 3 * ns; e += blockDim.x) {
+  for (int e = threadIdx.x; e < 3 * ns; e += bd) {
     const int sj = e / 3, c = e - 3 * sj;
     double v = 0.0;
     for (int q = 0; q < parts; ++q) v += Pa[((size_t)q * ns + sj) * 3 + c];
@@ -370,10 +371,10 @@ __device__ __forceinline__ void span_block(const MarkerArgs& __restrict__ a, int
   }
 }
 
-__global__ void __launch_bounds__(256) k_span(Group gr) {
+__global__ void __launch_bounds__(512) k_interp_span(Group gr) {
   int lb;
   const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
-  span_block(*a, lb);
+  interp_span_block(*a, lb);
 }
 
 // Block (foil, span layer s): the perimeter part of the solve,
@@ -473,6 +474,8 @@ __global__ void __launch_bounds__(256) k_layer(Group gr) {
   layer_block(*a, lb);
 }
 
+size_t marker_span_lds(int ns) { return interp_span_lds(ns, span_threads(ns)); }
+
 static hipError_t raise_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -501,11 +504,10 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
                           hipStream_t s) {
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
   int nb[kMaxGroup], nl[kMaxGroup], np[kMaxGroup];
-  size_t lds_i = 0, lds_l = 0, lds_s = 0;
+  size_t lds_l = 0, lds_s = 0;
   for (int j = 0; j < n; ++j) {
     const MarkerArgs& a = *host[j];
     int maxnp = 0, layers = 0, perims = 0, maxcells = 0;
-    const int ns = a.g.nz;
     for (int k = 0; k < a.nw; ++k) {
       maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
       layers += a.w[k].ns;
@@ -513,23 +515,22 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
       const int c = a.w[k].bw * a.w[k].bh;
       maxcells = c > maxcells ? c : maxcells;
     }
-    const size_t li = ((size_t)kPw * maxnp + 4 * (size_t)maxcells) * sizeof(double);
     const size_t ll = ((size_t)maxnp * maxnp + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
                       (size_t)a.copies * maxcells * 3 * sizeof(float);
-    const int groups = (ns + 3) / 4;
-    int parts = 256 / groups;
-    parts = parts < 1 ? 1 : (parts > 8 ? 8 : parts);
-    const size_t ls = (5 + 3 * (size_t)parts) * (size_t)ns * sizeof(double);
-    lds_i = li > lds_i ? li : lds_i;
     lds_l = ll > lds_l ? ll : lds_l;
-    lds_s = ls > lds_s ? ls : lds_s;
     nb[j] = a.band_blocks;   // 4 box rows per block
     nl[j] = layers;
     np[j] = perims;
   }
-  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_interp), lds_i);
-  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
-  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_span), lds_s);
+  // one block size for the group: 512 threads unless a solve's span needs 256
+  int thr = 512;
+  for (int j = 0; j < n; ++j) thr = span_threads(host[j]->g.nz) < thr ? span_threads(host[j]->g.nz) : thr;
+  for (int j = 0; j < n; ++j) {
+    const size_t ls = interp_span_lds(host[j]->g.nz, thr);
+    lds_s = ls > lds_s ? ls : lds_s;
+  }
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
+  if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_interp_span), lds_s);
   if (e != hipSuccess) return e;
   Group g;
   int total = group_fill(g, dev, nb, n);
@@ -542,16 +543,12 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  total = group_fill(g, dev, nl, n);
-  if (total == 0) return hipSuccess;
-  k_interp<<<total, 256, lds_i, s>>>(g);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   const int tp = group_fill(g, dev, np, n);
-  k_span<<<tp, 256, lds_s, s>>>(g);
+  if (tp == 0) return hipSuccess;
+  k_interp_span<<<tp, thr, lds_s, s>>>(g);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  group_fill(g, dev, nl, n);
+  total = group_fill(g, dev, nl, n);
   k_layer<<<total, 256, lds_l, s>>>(g);
   return hipGetLastError();
 }

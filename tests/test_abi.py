@@ -144,3 +144,22 @@ def test_one_layer_span_is_accepted_only_periodic():
     walls = dict(bx, nz=2, bc=[WL.VELOCITY, WL.PRESSURE, WL.WALL, WL.WALL, WL.WALL, WL.WALL])
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(walls)), 0, None) == 0
     assert b"periodic" in lib.ibmlbm_last_error(None)
+
+
+def test_span_longer_than_the_marker_block_is_rejected():
+    """One block holds every span layer of a marker (its band records, B and
+    the span solve) in local memory, so spans have a limit; the lattice alone
+    has none, and the limit is named in the error."""
+    L, lib = _lib()
+    bx, wg = _plate()
+    from paper_2102_01305_amd.solver import make_wings
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=384))), 1, make_wings(wg)) > 0
+    long_span = dict(bx, nz=1024)
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(long_span)), 0, None) > 0
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(long_span)), 1, make_wings(wg)) == 0
+    msg = lib.ibmlbm_last_error(None).decode()
+    assert "span of 1024 layers" in msg
+    top = int(msg.rsplit("at most ", 1)[1].rstrip(")"))
+    assert 384 <= top < 1024
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top))), 1, make_wings(wg)) > 0
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top + 1))), 1, make_wings(wg)) == 0
