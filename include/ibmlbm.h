@@ -154,9 +154,11 @@ IBMLBM_API int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u
  * foil's perimeter gets round(P/ds) markers at equal arc length; the
  * surface element is P/round(P/ds) x 1.  EINVAL if a marker support could
  * leave the box on a non-periodic axis, if the span is not periodic, if
- * two foils' supports could overlap during the motion, or if a foil's
- * perimeter system (Eq. 18) is numerically singular.  ENOMEM if the
- * workspace cannot hold the markers. */
+ * two foils' supports could overlap during the motion, if a foil's
+ * perimeter system (Eq. 18) is numerically singular, or if the span has more
+ * layers than one marker's interpolation block holds in local memory (the
+ * message names the limit, about 425 layers).  ENOMEM if the workspace
+ * cannot hold the markers. */
 IBMLBM_API int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings);
 
 /* Enqueue n time steps (Sec. 2.2): streaming, moments, marker kinematics at
