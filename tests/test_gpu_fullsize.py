@@ -59,3 +59,30 @@ def test_clap_fling_full_size(storage, bar_u, bar_c):
     assert e <= bar_u
     assert dc["cl"] <= bar_c
     assert dc["ct"] <= bar_c
+
+
+def test_large_config_properties():
+    """The largest workload, 512x384x384 with two c = 40 wings (2 x 84 x 384
+    markers), too large for the oracle: properties that hold at any size.
+    Started at rest (plus the free stream) from mid-stroke, the pair stays
+    mirror-symmetric, so F_x agree and F_y are opposite for the two wings at
+    every step; and the FP16 run follows the FP32 run within the FP16
+    storage bar over the whole box."""
+    _say("clap & fling 512x384x384, c=40, 10 steps from step 37, fp32 and fp16")
+    bx, wg, ph = WL.clap_fling_case(nx=512, ny=384, nz=384, chord=40.0, re=150.0, j=0.01, f=0.25)
+    u0 = np.zeros((3, bx["nz"], bx["ny"], bx["nx"]))
+    runs = {}
+    for storage in ("fp32", "fp16"):
+        gpu = gpu_solver(bx, wg, ph, u0=u0, step0=37, storage=storage)
+        gpu.step(10)
+        runs[storage] = (gpu.forces(37, 10), gpu.fields("u"))
+        gpu.close()
+    h, u32 = runs["fp32"]
+    assert np.isfinite(h).all() and np.isfinite(u32).all()
+    scale = np.abs(h[:, :, :2]).max()
+    sym_x = np.abs(h[:, 0, 0] - h[:, 1, 0]).max() / scale
+    sym_y = np.abs(h[:, 0, 1] + h[:, 1, 1]).max() / scale
+    e16 = l2rel(runs["fp16"][1], u32)
+    print(f"[large] mirror Fx {sym_x:.2e} Fy {sym_y:.2e}; fp16 vs fp32 L2 rel u {e16:.2e}", flush=True)
+    assert sym_x <= 1e-4 and sym_y <= 1e-4
+    assert e16 <= 1e-3
