@@ -159,13 +159,10 @@ class SweepServer:
         results = {}
         used = 0
         fp_cache = {}
-        while pending or waiting or active:
-            t = now()
-            while pending and pending[0].arrival <= t:
-                waiting.append(pending.popleft())
-            prefetch()
+        def admit():
             # admission, in arrival order: a request waits for memory rather
             # than being overtaken by a smaller one
+            nonlocal used
             while waiting and len(active) < self.max_batch:
                 r = waiting[0]
                 fp = fp_cache.get(r.rid)
@@ -174,7 +171,8 @@ class SweepServer:
                 if fp == 0 or fp > self.budget:
                     waiting.popleft()
                     why = "invalid solve description" if fp == 0 else "larger than the HBM budget"
-                    results[r.rid] = SweepResult(r.rid, r.arrival, t, now(), 0, 0, None, why)
+                    t = now()
+                    results[r.rid] = SweepResult(r.rid, r.arrival, t, t, 0, 0, None, why)
                     continue
                 if used + fp > self.budget:
                     break
@@ -186,16 +184,27 @@ class SweepServer:
                 active.append(_Active(r, s, now(), fp=fp))
                 if log:
                     log(f"admit {r.rid} at {now():.3f}s ({len(active)} active, {used / 2**20:.0f} MiB)")
+
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            prefetch()
+            # one round: the next chunk of the running solves is enqueued
+            # first, so that setting up newly admitted solves (on the side
+            # stream) overlaps it; those join from the next round on
+            stepping = list(active)
+            k = min(self.chunk, min(a.req.steps - a.done for a in stepping)) if stepping else 0
+            if k > 0:
+                self.backend.step([a.solver for a in stepping], k)
+                self.batch_sizes.append(len(stepping))
+                for a in stepping:
+                    a.done += k
+            admit()
             if not active:
                 if pending:
                     time.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            k = min(self.chunk, min(a.req.steps - a.done for a in active))
-            if k > 0:
-                self.backend.step([a.solver for a in active], k)
-                self.batch_sizes.append(len(active))
-                for a in active:
-                    a.done += k
             keep = []
             for a in active:
                 if a.done < a.req.steps:
