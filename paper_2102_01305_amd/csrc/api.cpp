@@ -650,7 +650,7 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     b.band = ma.w[w].band;
     b.corr = ma.w[w].corr;
     cells += (long long)b.w * b.h * c.nz;
-    box_rows += (long long)ma.w[w].bh * c.nz;
+    box_rows += (long long)(ma.w[w].bw <= 32 ? (ma.w[w].bh + 1) / 2 : ma.w[w].bh) * c.nz;   // band waves
     maxnp = std::max(maxnp, ma.w[w].np);
     maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
   }

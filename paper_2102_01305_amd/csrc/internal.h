@@ -102,7 +102,7 @@ struct MarkerArgs {
   int nw;
   int m_total;
   int band_cells;            // sum over foils of bw*bh*nz
-  int band_blocks;           // blocks of 4 box rows
+  int band_blocks;           // blocks of 4 band waves (a row each, or two rows of a box <= 32 wide)
   WingDev w[kMaxWings];
   double wz[4];              // span weights of a node at offsets -1.5, -0.5, 0.5, 1.5
   double t;

@@ -160,7 +160,8 @@ __global__ void __launch_bounds__(256) k_factor(Group gr) {
 
 // rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
 // pre-collision state at every node of every foil's box, on every layer.
-// One wave per box row (y, z), lanes along x, so rows are wave-uniform.
+// One wave per box row (y, z), lanes along x; a box at most 32 wide gives a
+// wave two neighbouring rows, one per half.
 template <class St>
 __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int lb) {
   using T = typename St::T;
@@ -168,27 +169,26 @@ __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int
   const int lane = threadIdx.x & 63;
   int wi = 0;
   while (wi < a.nw) {
-    const int rows = a.w[wi].bh * a.g.nz;
-    if (R < rows) break;
-    R -= rows;
+    const int units = (a.w[wi].bw <= 32 ? (a.w[wi].bh + 1) / 2 : a.w[wi].bh) * a.g.nz;
+    if (R < units) break;
+    R -= units;
     ++wi;
   }
   if (wi >= a.nw) return;
   const WingDev& w = a.w[wi];
-  const int ly = R % w.bh, z = R / w.bh;
+  const bool pair = w.bw <= 32;
+  const int per = pair ? (w.bh + 1) / 2 : w.bh;
+  const int z = R / per, q = R - z * per;
+  const int ly = pair ? 2 * q + (lane >> 5) : q;
+  const int lx0 = pair ? (lane & 31) : lane;
+  if (ly >= w.bh) return;
   float4* out = w.band + ((long long)z * w.side + ly) * w.side;
-  for (int lx = lane; lx < w.bw; lx += 64) {
+  for (int lx = lx0; lx < w.bw; lx += pair ? 32 : 64) {
     float f[kQ];
     pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
     zou_he<St, false>(a.g, a.p, w.x0 + lx, w.y0 + ly, z, f);
-    float drho = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) {
-      drho += f[i];
-      jx += cxq(i) * f[i];
-      jy += cyq(i) * f[i];
-      jz += czq(i) * f[i];
-    }
+    float drho, jx, jy, jz;
+    moments19(f, drho, jx, jy, jz);
     const float rho = 1.0f + drho;
     out[lx] = make_float4(rho, (jx + 0.5f * a.p.fb[0]) / rho, (jy + 0.5f * a.p.fb[1]) / rho,
                           (jz + 0.5f * a.p.fb[2]) / rho);
