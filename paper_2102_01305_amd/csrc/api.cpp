@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "kinematics.h"
 
 using namespace ibmk;
 
@@ -638,6 +639,10 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ma.win_t0 = h->win_t0;
   ma.slot = (int)(s - h->win_t0);
   ma.t = (double)s;
+  for (int k = 0; k < h->nw; ++k) {
+    double* q = ma.pose[k];
+    wing_pose(ma.w[k], (double)s, q[0], q[1], q[2], q[3], q[4], q[5]);
+  }
   ma.src = ca.src;
   ca.hist_row = s % c.history_steps;
   long long cells = 0, box_rows = 0;

@@ -106,6 +106,7 @@ struct MarkerArgs {
   WingDev w[kMaxWings];
   double wz[4];              // span weights of a node at offsets -1.5, -0.5, 0.5, 1.5
   double t;
+  double pose[kMaxWings][6]; // per foil at t: theta, dtheta/dt, pivot x, y, pivot velocity x, y
   const void* src;           // current state (post-collision of the previous step)
   const double* ref;
   const double* G;

@@ -9,6 +9,7 @@
 //  layer     the perimeter part of the solve, du_B, the force and moment of
 //            each layer (Eq. 26) and sum_l du_B D dA over the layer (Eq. 15).
 #include "lattice_dev.h"
+#include "kinematics.h"
 
 namespace ibmk {
 
@@ -29,42 +30,6 @@ constexpr int kPw = 14;
 __device__ __forceinline__ double delta_k(double r) {
   r = fabs(r);
   return r <= 2.0 ? 0.25 * (1.0 + cos(0.5 * M_PI * r)) : 0.0;
-}
-
-// Chord angle, its rate, pivot position and velocity at time t
-// (Eqs. 20-21, 23; ABS_SIN takes the forward derivative at the kinks, the
-// kink located from the half-period phase so that every side agrees).
-__device__ void wing_pose(const WingDev& w, double t, double& th, double& thd, double& hx,
-                          double& hy, double& vx, double& vy) {
-  double al = w.mean, ald = 0.0;
-  if (w.shape != 0) {
-    const double om = 2.0 * M_PI / w.period;
-    if (w.shape == 1) {
-      const double arg = om * t + w.phase;
-      al = w.mean + w.amp * sin(arg);
-      ald = w.amp * om * cos(arg);
-    } else {
-      const double psi = t / w.period + w.phase / (2.0 * M_PI);
-      const double h = psi - floor(2.0 * psi) / 2.0;
-      al = w.mean + w.amp * sin(2.0 * M_PI * h);
-      ald = w.amp * om * cos(2.0 * M_PI * h);
-    }
-  }
-  th = w.theta0 + w.sense * al;
-  thd = w.sense * ald;
-  hx = w.hinge0[0];
-  hy = w.hinge0[1];
-  vx = 0.0;
-  vy = 0.0;
-  if (w.tamp != 0.0) {
-    const double om = 2.0 * M_PI / w.period;
-    const double arg = om * t + w.phase;
-    const double cb = cos(w.tang), sb = sin(w.tang);
-    hx += w.tamp * cos(arg) * cb;
-    hy += w.tamp * cos(arg) * sb;
-    vx = -w.tamp * om * sin(arg) * cb;
-    vy = -w.tamp * om * sin(arg) * sb;
-  }
 }
 
 // a(p, q) = sum_j delta(j - X_p) delta(j - X_q) from the two 4-node weight
@@ -284,8 +249,7 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
     }
   }
   __syncthreads();
-  double th, thd, hx, hy, vx, vy;
-  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  const double thd = a.pose[wi][1], vx = a.pose[wi][4], vy = a.pose[wi][5];
   const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
   for (int z = threadIdx.x; z < ns; z += bd) {
     double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
@@ -417,8 +381,7 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
     Y[e] = y0 + y1;
   }
   __syncthreads();
-  double th, thd, hx, hy, vx, vy;
-  wing_pose(w, a.t, th, thd, hx, hy, vx, vy);
+  const double hx = a.pose[wi][2], hy = a.pose[wi][3];
   double fx = 0.0, fy = 0.0, fz = 0.0, mz = 0.0;
   for (int p = threadIdx.x; p < n; p += blockDim.x) {
     const double y0 = Y[3 * p], y1 = Y[3 * p + 1], y2 = Y[3 * p + 2];
