@@ -587,6 +587,15 @@ int record_event(ibmlbm_t h, hipStream_t st, int kind, bool start, double cells 
 // Arguments of step s whose current state is A if cur_A: the parts that
 // never change for this handle, then the step's own (state buffers, time,
 // window slot, force-history row, node boxes and the grids they imply).
+// Multiplier m with umulhi(n, m) = n / d for every 0 <= n < n_end: with
+// m = floor(2^32 / d) + 1, n m / 2^32 = n / d + n (d - 2^32 mod d) / (d 2^32),
+// and the second term stays below 1/d while n d < 2^32.  0 where that does
+// not hold (or d = 1), and the kernel divides.
+unsigned div_mul(unsigned long long d, unsigned long long n_end) {
+  if (d < 2 || n_end * d >= (1ULL << 32)) return 0;
+  return (unsigned)((1ULL << 32) / d + 1);
+}
+
 void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs& ma) {
   const LatticeLayout& L = h->L;
   const ibmlbm_config& c = h->cfg;
@@ -602,6 +611,8 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     ma.wz[0] = delta_h(1.5); ma.wz[1] = delta_h(0.5); ma.wz[2] = delta_h(0.5); ma.wz[3] = delta_h(1.5);
   }
   ca.nblocks = L.nblocks;
+  ca.nxc_mul = div_mul(L.nxc, (unsigned long long)L.nblocks * kBlockRows);
+  ca.ny_mul = div_mul(c.ny, (unsigned long long)c.ny * c.nz);
   ca.face_blocks = L.face_blocks;
   ca.mass_part = at<double>(h, L.mass_part);
   ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);

@@ -39,8 +39,18 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   constexpr float kS = St::kS, kInv = St::kInv;
   const Geo& g = a.g;
   float f[kQ];
-  pull19<St, true>(S, g, x, y, z, f);
-  if (ZH) zou_he<St, true>(g, a.p, x, y, z, f);
+  if constexpr (ZH) {
+    pull19<St, true>(S, g, x, y, z, f);   // per-thread rows
+    zou_he<St, true>(g, a.p, x, y, z, f);
+  } else {
+    // wave-uniform row.  16-bit storage, which is bound by instruction
+    // issue, takes the scalar-base pull where no y or z wall reflects into
+    // the row; FP32, bound by memory, measured faster with the general pull
+    if (sizeof(T) == 2 && pull_rows_inside(g, y, z))
+      pull19_rows<St>(S, g, x, y, z, f);
+    else
+      pull19<St, true>(S, g, x, y, z, f);
+  }
   float dr, jx, jy, jz;                            // kS drho, kS j
   moments19(f, dr, jx, jy, jz);
   const float drho = dr * kInv;
@@ -191,8 +201,8 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   int xc, row;
   if (sizeof(T) == 2) {
     const int gw = __builtin_amdgcn_readfirstlane(lb * kBlockRows + (int)threadIdx.y);
-    xc = gw % a.nxc;
-    row = gw / a.nxc;
+    row = a.nxc_mul ? (int)__umulhi((unsigned)gw, a.nxc_mul) : gw / a.nxc;
+    xc = gw - row * a.nxc;
   } else {
     // Workgroups are dealt to the 8 XCDs in turn; a single solve's tiles are
     // reordered so that each XCD takes runs of 4 block rows (all chunks of
@@ -218,7 +228,8 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   double dm = 0.0;
   bool bad = false;
   if (active) {
-    const int z = __builtin_amdgcn_readfirstlane(row / g.ny);
+    const int z = __builtin_amdgcn_readfirstlane(
+        sizeof(T) == 2 && a.ny_mul ? (int)__umulhi((unsigned)row, a.ny_mul) : row / g.ny);
     const int y = __builtin_amdgcn_readfirstlane(row - z * g.ny);
     const float drho = collide_cell<St, IBM, FORCE>(a, S, D, x, y, z);
     if (CHECK) {

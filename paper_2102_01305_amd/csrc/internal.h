@@ -69,6 +69,9 @@ struct CollideArgs {
   float wz[4];               // span weights delta(1.5), delta(0.5), delta(0.5), delta(1.5)
   int nxc;                   // 64-wide chunks along x
   int nblocks;               // row groups of 4 rows x 64 cells
+  // n / nxc and n / ny as umulhi(n, m) for the wave indices the kernel
+  // divides (m = floor(2^32 / d) + 1, exact when n d < 2^32; 0: divide)
+  unsigned nxc_mul, ny_mul;
   int face_blocks;           // blocks of the Zou-He face launch (0: no such face)
   double* mass_part;         // per-block partial sums (check steps); face blocks after nblocks
   int* flags;                // bit 0: non-finite density seen

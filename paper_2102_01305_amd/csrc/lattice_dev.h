@@ -149,6 +149,56 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
   for (int i = 0; i < kQ; ++i) f[i] = RAW ? St::ldr(src[i]) : St::ld(src[i]);
 }
 
+// pull19 for a wave-uniform row (y, z) whose sources all lie inside the box
+// or across a periodic face (no y or z wall reflects into it; see
+// pull_rows_inside): the 9 source rows (y - c_y, z - c_z) are wrapped once
+// in scalar registers and each population row is a scalar base plus the
+// lane's 32-bit offset, so the wraps and row products cost no per-cell
+// instructions.  The x-face lanes first load c_x = -/+1 from x -/+ 1 of the
+// same row (the padding beside the row, in bounds) and then take the ghost
+// record in a second, masked load.  Same sources as pull19.
+__device__ __forceinline__ bool pull_rows_inside(const Geo& g, int y, int z) {
+  return (g.yper || (y > 0 && y < g.ny - 1)) && (g.zper || (z > 0 && z < g.nz - 1));
+}
+template <class St>
+__device__ __forceinline__ void pull19_rows(const typename St::T* __restrict__ S, const Geo& g,
+                                            int x, int y, int z, float f[kQ]) {
+  using T = typename St::T;
+  constexpr unsigned es = sizeof(T);
+  const char* Sb = reinterpret_cast<const char*>(S);
+  const unsigned rowb = (unsigned)kQ * (unsigned)g.px * es, popb = (unsigned)g.px * es;
+  const unsigned xo = (unsigned)x * es;
+  // source row of direction (c_y, c_z), c in {-1, 0, 1}: index [1 - c]
+  const int ys[3] = {y == 0 ? g.ny - 1 : y - 1, y, y == g.ny - 1 ? 0 : y + 1};   // y - c_y
+  const int zs[3] = {z == 0 ? g.nz - 1 : z - 1, z, z == g.nz - 1 ? 0 : z + 1};   // z - c_z
+  const char* base[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+      base[a][b] = Sb + (unsigned long long)(unsigned)(zs[b] * g.ny + ys[a] + 1) * rowb;
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const unsigned q = (unsigned)i * popb - (unsigned)(cxq(i) * (int)es);
+    f[i] = St::ldr(reinterpret_cast<const T*>(base[1 - cyq(i)][1 - czq(i)] + (xo + q)));
+  }
+  constexpr int per = 32 / (int)sizeof(T);
+  const T* gb = reinterpret_cast<const T*>(Sb + g.goff);
+  const long long rows = (long long)g.ny * g.nz;
+  if (x == 0) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      if (cxq(i) == 1)
+        f[i] = St::ldr(gb + (long long)(zs[1 - czq(i)] * g.ny + ys[1 - cyq(i)]) * per + xslot(i));
+  }
+  if (x == g.nx - 1) {
+#pragma unroll
+    for (int i = 0; i < kQ; ++i)
+      if (cxq(i) == -1)
+        f[i] = St::ldr(gb + (rows + zs[1 - czq(i)] * g.ny + ys[1 - cyq(i)]) * per + xslot(i));
+  }
+}
+
 // Global-memory view of a pointer.  Loads through it are global loads, which
 // the compiler knows cannot alias LDS; through a generic pointer each load
 // of a global-to-LDS copy would wait for the one before it.
