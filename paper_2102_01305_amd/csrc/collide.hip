@@ -43,10 +43,9 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
     pull19<St, true>(S, g, x, y, z, f);   // per-thread rows
     zou_he<St, true>(g, a.p, x, y, z, f);
   } else {
-    // wave-uniform row.  16-bit storage, which is bound by instruction
-    // issue, takes the scalar-base pull where no y or z wall reflects into
-    // the row; FP32, bound by memory, measured faster with the general pull
-    if (sizeof(T) == 2 && pull_rows_inside(g, y, z))
+    // wave-uniform row: the scalar-base pull where no y or z wall reflects
+    // into the row
+    if (pull_rows_inside(g, y, z))
       pull19_rows<St>(S, g, x, y, z, f);
     else
       pull19<St, true>(S, g, x, y, z, f);

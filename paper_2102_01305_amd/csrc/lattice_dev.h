@@ -154,9 +154,8 @@ __device__ __forceinline__ void pull19(const typename St::T* __restrict__ S, con
 // pull_rows_inside): the 9 source rows (y - c_y, z - c_z) are wrapped once
 // in scalar registers and each population row is a scalar base plus the
 // lane's 32-bit offset, so the wraps and row products cost no per-cell
-// instructions.  The x-face lanes first load c_x = -/+1 from x -/+ 1 of the
-// same row (the padding beside the row, in bounds) and then take the ghost
-// record in a second, masked load.  Same sources as pull19.
+// instructions; only the c_x = -/+1 rows select the ghost record per lane
+// at the x faces.  Same sources as pull19.
 __device__ __forceinline__ bool pull_rows_inside(const Geo& g, int y, int z) {
   return (g.yper || (y > 0 && y < g.ny - 1)) && (g.zper || (z > 0 && z < g.nz - 1));
 }
@@ -177,25 +176,17 @@ __device__ __forceinline__ void pull19_rows(const typename St::T* __restrict__ S
 #pragma unroll
     for (int b = 0; b < 3; ++b)
       base[a][b] = Sb + (unsigned long long)(unsigned)(zs[b] * g.ny + ys[a] + 1) * rowb;
-#pragma unroll
-  for (int i = 0; i < kQ; ++i) {
-    const unsigned q = (unsigned)i * popb - (unsigned)(cxq(i) * (int)es);
-    f[i] = St::ldr(reinterpret_cast<const T*>(base[1 - cyq(i)][1 - czq(i)] + (xo + q)));
-  }
   constexpr int per = 32 / (int)sizeof(T);
   const T* gb = reinterpret_cast<const T*>(Sb + g.goff);
   const long long rows = (long long)g.ny * g.nz;
-  if (x == 0) {
 #pragma unroll
-    for (int i = 0; i < kQ; ++i)
-      if (cxq(i) == 1)
-        f[i] = St::ldr(gb + (long long)(zs[1 - czq(i)] * g.ny + ys[1 - cyq(i)]) * per + xslot(i));
-  }
-  if (x == g.nx - 1) {
-#pragma unroll
-    for (int i = 0; i < kQ; ++i)
-      if (cxq(i) == -1)
-        f[i] = St::ldr(gb + (rows + zs[1 - czq(i)] * g.ny + ys[1 - cyq(i)]) * per + xslot(i));
+  for (int i = 0; i < kQ; ++i) {
+    const unsigned q = (unsigned)i * popb - (unsigned)(cxq(i) * (int)es);
+    const T* pp = reinterpret_cast<const T*>(base[1 - cyq(i)][1 - czq(i)] + (xo + q));
+    const long long gr = (long long)(zs[1 - czq(i)] * g.ny + ys[1 - cyq(i)]);   // source row
+    if (cxq(i) == 1) pp = x == 0 ? gb + gr * per + xslot(i) : pp;
+    if (cxq(i) == -1) pp = x == g.nx - 1 ? gb + (rows + gr) * per + xslot(i) : pp;
+    f[i] = St::ldr(pp);
   }
 }
 
