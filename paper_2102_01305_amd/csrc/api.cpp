@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "divmul.h"
 #include "internal.h"
 #include "kinematics.h"
 
@@ -587,15 +588,6 @@ int record_event(ibmlbm_t h, hipStream_t st, int kind, bool start, double cells 
 // Arguments of step s whose current state is A if cur_A: the parts that
 // never change for this handle, then the step's own (state buffers, time,
 // window slot, force-history row, node boxes and the grids they imply).
-// Multiplier m with umulhi(n, m) = n / d for every 0 <= n < n_end: with
-// m = floor(2^32 / d) + 1, n m / 2^32 = n / d + n (d - 2^32 mod d) / (d 2^32),
-// and the second term stays below 1/d while n d < 2^32.  0 where that does
-// not hold (or d = 1), and the kernel divides.
-unsigned div_mul(unsigned long long d, unsigned long long n_end) {
-  if (d < 2 || n_end * d >= (1ULL << 32)) return 0;
-  return (unsigned)((1ULL << 32) / d + 1);
-}
-
 void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs& ma) {
   const LatticeLayout& L = h->L;
   const ibmlbm_config& c = h->cfg;
