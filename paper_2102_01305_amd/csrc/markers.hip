@@ -309,6 +309,7 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
       // output s0 + j takes G[(s0 + j - s2) mod ns]
       double g0 = G[(s0 - lo + ns) % ns], g1 = G[(s0 + 1 - lo + ns) % ns],
              g2 = G[(s0 + 2 - lo + ns) % ns], g3 = G[(s0 + 3 - lo + ns) % ns];
+#pragma unroll 4
       for (int s2 = lo; s2 < hi; ++s2) {
         const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
         acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
