@@ -7,7 +7,8 @@ default workload is the clap & fling pair (chord 20, aspect 5) in a
 256x192x192 box at Re = 100, J = 0.01, f = 0.25, FP32 storage, synthetic
 seeded initial noise.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--workload cf|large|plate]
+    python bench.py [--steps K] [--warmup W]
+                    [--workload cf|large|plate|tgv|fig8_2d|cylinder]
                     [--storage fp32|fp16|bf16] [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -40,6 +41,15 @@ def workload(name):
     if name == "plate":
         bx, wg, ph = WL.plate_case()
         return "plate_64x32x32", bx, wg, ph
+    if name == "fig8_2d":
+        # the figure-eight hover in the 2D mode (one periodic layer) at the
+        # paper's domain of 50 c x 25 c with c = 20
+        bx, wg, ph = WL.figure_eight_case(nx=1000, ny=500, nz=1, chord=20.0)
+        return "figure_eight_2d_1000x500", bx, wg, ph
+    if name == "cylinder":
+        # stationary cylinder between Zou-He velocity and pressure faces
+        bx, wg, ph = WL.cylinder_case(nx=256, ny=192, nz=192, d=20.0, re=10.0, u_inf=0.04)
+        return "cylinder_zou_he_256x192x192", bx, wg, ph
     if name == "tgv":
         bx, r0, u0, nu = WL.taylor_green_case(256)
         return "taylor_green_256", bx, [], dict(kind="taylor_green", re=100.0, rho0=r0, u0=u0)

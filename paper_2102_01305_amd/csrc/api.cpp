@@ -34,7 +34,7 @@ struct LatticeLayout {
   size_t total = 0;      // elements of the slabs of one state buffer
   size_t goff = 0;       // byte offset of the ghost records in a state buffer
   size_t N = 0;
-  int nxc = 0, nblocks = 0, face_blocks = 0;
+  int nxc = 0, nblocks = 0;
   Region fA, fB, mass_part, diag, argtab;
   size_t end = 0;
 };
@@ -168,15 +168,13 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   L.N = (size_t)c->nx * c->ny * c->nz;
   L.nxc = (c->nx + kBlockX - 1) / kBlockX;
   L.nblocks = L.nxc * ((c->ny * c->nz + kBlockRows - 1) / kBlockRows);
-  const int zh_faces = (c->bc[0] >= IBMLBM_BC_ZH_VELOCITY) + (c->bc[1] >= IBMLBM_BC_ZH_VELOCITY);
-  L.face_blocks = (int)(((long long)zh_faces * c->ny * c->nz + 255) / 256);
   size_t o = 0;
   auto take = [&](Region& r, size_t bytes) { r.off = o; r.bytes = bytes; o = align256(o + bytes); };
   L.goff = align256(L.total * L.es);
   const size_t state = L.goff + 2 * (size_t)c->ny * c->nz * 32;
   take(L.fA, state);
   take(L.fB, state);
-  take(L.mass_part, (size_t)(L.nblocks + L.face_blocks) * sizeof(double));
+  take(L.mass_part, (size_t)L.nblocks * sizeof(double));
   take(L.diag, 64);
   take(L.argtab, (size_t)kFactorWindow * kArgSlotBytes);
   L.end = o;
@@ -605,7 +603,6 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ca.nblocks = L.nblocks;
   ca.nxc_mul = div_mul(L.nxc, (unsigned long long)L.nblocks * kBlockRows);
   ca.ny_mul = div_mul(c.ny, (unsigned long long)c.ny * c.nz);
-  ca.face_blocks = L.face_blocks;
   ca.mass_part = at<double>(h, L.mass_part);
   ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
   void* A = h->ws + L.fA.off;
@@ -705,6 +702,12 @@ bool has_force(const ibmlbm_config& c) {
   return c.body_force[0] != 0.0 || c.body_force[1] != 0.0 || c.body_force[2] != 0.0;
 }
 
+// Zou-He x faces: their cells are rebuilt inside the collide kernel, by its
+// instantiation for such solves.
+bool has_zou_he(const ibmlbm_config& c) {
+  return c.bc[0] >= IBMLBM_BC_ZH_VELOCITY || c.bc[1] >= IBMLBM_BC_ZH_VELOCITY;
+}
+
 // `steps` time steps of every handle in hs (one stream).  Each stage of a
 // step is one grouped launch over the handles that share its kernel
 // instantiation, so small solves fill the device together and each solve
@@ -765,22 +768,24 @@ int run_steps(ibmlbm_t* hs, int n, int steps) {
       int rc = record_event(hs[0], st, 0, true, (double)hs[0]->L.N);
       if (rc) return rc;
     }
-    for (int key = 0; key < 24; ++key) {
-      const int sto = key >> 3;
-      const bool ibm = key & 4, force = key & 2, check = key & 1;
+    for (int key = 0; key < 48; ++key) {
+      const int sto = key >> 4;
+      const bool zh = key & 8, ibm = key & 4, force = key & 2, check = key & 1;
       chh.clear();
       dv.clear();
       for (int j = 0; j < n; ++j) {
         ibmlbm_t h = hs[j];
         const ibmlbm_config& c = h->cfg;
         const bool ck = c.check_interval > 0 && ((h->step + 1) % c.check_interval == 0);
-        if (c.storage != sto || (h->nw > 0) != ibm || has_force(c) != force || ck != check) continue;
+        if (c.storage != sto || (h->nw > 0) != ibm || has_force(c) != force || ck != check ||
+            has_zou_he(c) != zh)
+          continue;
         const int slot = (int)(h->step - h->win_t0);
         chh.push_back(&h->wca[slot]);
         dv.push_back(dev_ca(h, slot));
       }
       if (chh.empty()) continue;
-      hipError_t e = launch_collide(sto, ibm, force, check, chh.data(), dv.data(), (int)chh.size(), st);
+      hipError_t e = launch_collide(sto, ibm, force, check, zh, chh.data(), dv.data(), (int)chh.size(), st);
       if (e != hipSuccess) return fail(hs[0], IBMLBM_EDEVICE, "collide launch: %s", hipGetErrorString(e));
     }
     if (timed) {
@@ -792,7 +797,7 @@ int run_steps(ibmlbm_t* hs, int n, int steps) {
       const ibmlbm_config& c = h->cfg;
       const long long s = h->step;
       if (c.check_interval > 0 && ((s + 1) % c.check_interval == 0))
-        HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks + h->L.face_blocks,
+        HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks,
                                       (double)h->L.N,
                                       reinterpret_cast<double*>(h->ws + h->L.diag.off), s + 1, st));
       h->cur_is_A = !h->cur_is_A;

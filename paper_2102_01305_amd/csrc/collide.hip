@@ -2,9 +2,10 @@
 //
 //  collide   fused pull-streaming, moments, IBM velocity correction, Guo
 //            forcing and BGK relaxation over every cell (Eqs. 1-11, 16, 26);
-//            also writes the x-face ghost layer of the next state; on steps
-//            with foils, block 0 makes the fixed-order force sum and the
-//            coefficients.
+//            rebuilds the entering populations of Zou-He face cells where a
+//            solve has such faces; writes the x-face ghost layer of the next
+//            state; on steps with foils, block 0 makes the fixed-order force
+//            sum and the coefficients.
 //  ghost     the same ghost rule for a freshly initialised state.
 //  init_eq   equilibrium initial state from rho, u.
 //  moments   rho and velocity of every cell (read-back).
@@ -24,7 +25,8 @@ __device__ __forceinline__ bool in_box(const FoilBox& b, int x, int y) {
   return y >= b.y0 && y < b.y0 + b.h && x >= b.x0 && x < b.x0 + b.w;
 }
 
-// One cell update: pull-streaming, moments, optional IBM velocity
+// One cell update: pull-streaming, the Zou-He rebuild at the x faces (ZH:
+// the solve has Zou-He faces), moments, optional IBM velocity
 // correction and Guo forcing, BGK relaxation, streaming store of the
 // post-collision values and, at x = 0 / nx-1, the ghost layer of the next
 // state.  Returns the density deviation of the pre-collision state.
@@ -39,16 +41,20 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   constexpr float kS = St::kS, kInv = St::kInv;
   const Geo& g = a.g;
   float f[kQ];
+  // wave-uniform row: the scalar-base pull where no y or z wall reflects
+  // into the row
+  if (pull_rows_inside(g, y, z))
+    pull19_rows<St>(S, g, x, y, z, f);
+  else
+    pull19<St, true>(S, g, x, y, z, f);
   if constexpr (ZH) {
-    pull19<St, true>(S, g, x, y, z, f);   // per-thread rows
-    zou_he<St, true>(g, a.p, x, y, z, f);
-  } else {
-    // wave-uniform row: the scalar-base pull where no y or z wall reflects
-    // into the row
-    if (pull_rows_inside(g, y, z))
-      pull19_rows<St>(S, g, x, y, z, f);
-    else
-      pull19<St, true>(S, g, x, y, z, f);
+    // Zou-He x faces: rebuild the entering populations at the face lanes
+    // (the rule of zou_he, each face's branch on its own so the rest of
+    // the row keeps f in registers)
+    if ((g.yper || (y > 0 && y < g.ny - 1)) && (g.zper || (z > 0 && z < g.nz - 1))) {
+      if (x == 0 && g.bclo >= BC_ZH_VELOCITY) zou_he_face<St, true, 1>(a.p, g.bclo, f);
+      if (x == g.nx - 1 && x != 0 && g.bchi >= BC_ZH_VELOCITY) zou_he_face<St, true, -1>(a.p, g.bchi, f);
+    }
   }
   float dr, jx, jy, jz;                            // kS drho, kS j
   moments19(f, dr, jx, jy, jz);
@@ -183,7 +189,7 @@ __device__ void reduce_forces(const CollideArgs& a) {
 }
 
 // Every cell, one row per wave, 64 cells along x per wave, 4 waves per block.
-template <class St, bool IBM, bool FORCE, bool CHECK>
+template <class St, bool IBM, bool FORCE, bool CHECK, bool ZH>
 __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a, int lb,
                                               const void* src, void* dst) {
   using T = typename St::T;
@@ -221,16 +227,14 @@ __device__ __forceinline__ void collide_block(const CollideArgs& __restrict__ a,
   const int x = xc * kBlockX + threadIdx.x;
   // one row per wave: make the row index wave-uniform for the compiler
   row = __builtin_amdgcn_readfirstlane(row);
-  // cells on a Zou-He face are left to the face launch
-  const bool zh = (x == 0 && g.bclo >= BC_ZH_VELOCITY) || (x == g.nx - 1 && g.bchi >= BC_ZH_VELOCITY);
-  const bool active = x < g.nx && row < g.ny * g.nz && !zh;
+  const bool active = x < g.nx && row < g.ny * g.nz;
   double dm = 0.0;
   bool bad = false;
   if (active) {
     const int z = __builtin_amdgcn_readfirstlane(
         sizeof(T) == 2 && a.ny_mul ? (int)__umulhi((unsigned)row, a.ny_mul) : row / g.ny);
     const int y = __builtin_amdgcn_readfirstlane(row - z * g.ny);
-    const float drho = collide_cell<St, IBM, FORCE>(a, S, D, x, y, z);
+    const float drho = collide_cell<St, IBM, FORCE, ZH>(a, S, D, x, y, z);
     if (CHECK) {
       dm = (double)drho;
       bad = !isfinite(drho);
@@ -260,96 +264,57 @@ struct CollideGroup {
   void* dst[kMaxGroup];
 };
 
-template <class St, bool IBM, bool FORCE, bool CHECK>
+template <class St, bool IBM, bool FORCE, bool CHECK, bool ZH>
 __global__ void __launch_bounds__(kBlockX * kBlockRows)
 k_collide(CollideGroup gr) {
   int lb;
   const int k = group_index(gr.g, lb);
   const CollideArgs* a = static_cast<const CollideArgs*>(gr.g.args[k]);
-  collide_block<St, IBM, FORCE, CHECK>(*a, lb, gr.src[k], gr.dst[k]);
+  collide_block<St, IBM, FORCE, CHECK, ZH>(*a, lb, gr.src[k], gr.dst[k]);
 }
 
-// The cells of the Zou-He faces, one thread per (face, y, z), after the
-// collide launch of the same step (disjoint cells of the same states).
-template <class St, bool IBM, bool FORCE, bool CHECK>
-__global__ void __launch_bounds__(256) k_collide_face(CollideGroup gr) {
-  using T = typename St::T;
-  int lb;
-  const int k = group_index(gr.g, lb);
-  const CollideArgs& a = *static_cast<const CollideArgs*>(gr.g.args[k]);
-  const Geo& g = a.g;
-  const int rows = g.ny * g.nz;
-  const int nf = (g.bclo >= BC_ZH_VELOCITY) + (g.bchi >= BC_ZH_VELOCITY);
-  const int t = lb * 256 + (int)threadIdx.x;
-  double dm = 0.0;
-  bool bad = false;
-  if (t < nf * rows) {
-    const int face = t / rows, r = t - face * rows;
-    const bool lo_face = face == 0 && g.bclo >= BC_ZH_VELOCITY;
-    const int x = lo_face ? 0 : g.nx - 1;
-    const int z = r / g.ny, y = r - z * g.ny;
-    const float drho = collide_cell<St, IBM, FORCE, true>(a, static_cast<const T*>(gr.src[k]),
-                                                          static_cast<T*>(gr.dst[k]), x, y, z);
-    dm = (double)drho;
-    bad = !isfinite(drho);
+// One instantiation per (foils, body force, check step, Zou-He faces): the
+// solves without Zou-He faces run a kernel without the rebuild.
+template <class St, bool IBM, bool FORCE>
+static hipError_t launch_collide_c(bool check, bool zh, const CollideGroup& g, int blocks, hipStream_t s) {
+  const dim3 b(kBlockX, kBlockRows);
+  switch ((check ? 2 : 0) | (zh ? 1 : 0)) {
+    case 0: k_collide<St, IBM, FORCE, false, false><<<blocks, b, 0, s>>>(g); break;
+    case 1: k_collide<St, IBM, FORCE, false, true><<<blocks, b, 0, s>>>(g); break;
+    case 2: k_collide<St, IBM, FORCE, true, false><<<blocks, b, 0, s>>>(g); break;
+    default: k_collide<St, IBM, FORCE, true, true><<<blocks, b, 0, s>>>(g); break;
   }
-  if (CHECK) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) dm += __shfl_xor(dm, off);
-    __shared__ double part[4];
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dm;
-    if (bad) atomicOr(a.flags, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) a.mass_part[a.nblocks + lb] = part[0] + part[1] + part[2] + part[3];
-  }
-}
-
-template <class St, bool IBM, bool FORCE, bool CHECK>
-static hipError_t launch_collide_t(const CollideGroup& g, int blocks, const CollideGroup& gf,
-                                   int face_blocks, hipStream_t s) {
-  k_collide<St, IBM, FORCE, CHECK><<<blocks, dim3(kBlockX, kBlockRows), 0, s>>>(g);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || face_blocks == 0) return e;
-  k_collide_face<St, IBM, FORCE, CHECK><<<face_blocks, 256, 0, s>>>(gf);
   return hipGetLastError();
 }
 
 template <class St>
-static hipError_t launch_collide_s(bool ibm, bool force, bool check, const CollideGroup& g,
-                                   int blocks, const CollideGroup& gf, int face_blocks,
-                                   hipStream_t s) {
-  const int key = (ibm ? 4 : 0) | (force ? 2 : 0) | (check ? 1 : 0);
-  switch (key) {
-    case 0: return launch_collide_t<St, false, false, false>(g, blocks, gf, face_blocks, s);
-    case 1: return launch_collide_t<St, false, false, true>(g, blocks, gf, face_blocks, s);
-    case 2: return launch_collide_t<St, false, true, false>(g, blocks, gf, face_blocks, s);
-    case 3: return launch_collide_t<St, false, true, true>(g, blocks, gf, face_blocks, s);
-    case 4: return launch_collide_t<St, true, false, false>(g, blocks, gf, face_blocks, s);
-    case 5: return launch_collide_t<St, true, false, true>(g, blocks, gf, face_blocks, s);
-    case 6: return launch_collide_t<St, true, true, false>(g, blocks, gf, face_blocks, s);
-    default: return launch_collide_t<St, true, true, true>(g, blocks, gf, face_blocks, s);
+static hipError_t launch_collide_s(bool ibm, bool force, bool check, bool zh, const CollideGroup& g,
+                                   int blocks, hipStream_t s) {
+  switch ((ibm ? 2 : 0) | (force ? 1 : 0)) {
+    case 0: return launch_collide_c<St, false, false>(check, zh, g, blocks, s);
+    case 1: return launch_collide_c<St, false, true>(check, zh, g, blocks, s);
+    case 2: return launch_collide_c<St, true, false>(check, zh, g, blocks, s);
+    default: return launch_collide_c<St, true, true>(check, zh, g, blocks, s);
   }
 }
 
-hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
+hipError_t launch_collide(int storage, bool ibm, bool force, bool check, bool zh,
                           const CollideArgs* const* host, const void* const* dev, int n,
                           hipStream_t s) {
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  CollideGroup g, gf;
-  int blocks[kMaxGroup], fblocks[kMaxGroup];
+  CollideGroup g;
+  int blocks[kMaxGroup];
   for (int k = 0; k < n; ++k) {
     blocks[k] = host[k]->nblocks;
-    fblocks[k] = host[k]->face_blocks;
-    g.src[k] = gf.src[k] = host[k]->src;
-    g.dst[k] = gf.dst[k] = host[k]->dst;
+    g.src[k] = host[k]->src;
+    g.dst[k] = host[k]->dst;
   }
   const int total = group_fill(g.g, dev, blocks, n);
-  const int ftotal = group_fill(gf.g, dev, fblocks, n);
   if (total == 0) return hipSuccess;
   switch (storage) {
-    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, g, total, gf, ftotal, s);
-    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, g, total, gf, ftotal, s);
-    default: return launch_collide_s<StBF16>(ibm, force, check, g, total, gf, ftotal, s);
+    case ST_F32: return launch_collide_s<StF32>(ibm, force, check, zh, g, total, s);
+    case ST_F16: return launch_collide_s<StF16>(ibm, force, check, zh, g, total, s);
+    default: return launch_collide_s<StBF16>(ibm, force, check, zh, g, total, s);
   }
 }
 

@@ -72,7 +72,6 @@ struct CollideArgs {
   // n / nxc and n / ny as umulhi(n, m) for the wave indices the kernel
   // divides (m = floor(2^32 / d) + 1, exact when n d < 2^32; 0: divide)
   unsigned nxc_mul, ny_mul;
-  int face_blocks;           // blocks of the Zou-He face launch (0: no such face)
   double* mass_part;         // per-block partial sums (check steps); face blocks after nblocks
   int* flags;                // bit 0: non-finite density seen
   // force reduction by block 0 on steps with foils
@@ -141,7 +140,7 @@ struct Group {
 // launch wrappers (collide.hip, markers.hip); all enqueue on `s` and return
 // hipError_t.  `host[k]` is the host copy of the arguments that `dev[k]`
 // holds on the device (used for grid and LDS sizing only).
-hipError_t launch_collide(int storage, bool ibm, bool force, bool check,
+hipError_t launch_collide(int storage, bool ibm, bool force, bool check, bool zh,
                           const CollideArgs* const* host, const void* const* dev, int n,
                           hipStream_t s);
 hipError_t launch_ghost(int storage, const Geo& g, const Phys& p, void* buf, hipStream_t s);
