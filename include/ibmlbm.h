@@ -131,7 +131,9 @@ typedef struct {
 } ibmlbm_wing;
 
 /* Bytes of device workspace needed for cfg and the given foils (n_wings may
- * be 0).  Returns 0 if the configuration is invalid. */
+ * be 0).  Returns 0 if the configuration is invalid (among the limits:
+ * nx, ny >= 4; nx ny nz <= 2^34 cells; ny nz < 2^31 lattice rows;
+ * nx < 2^24). */
 IBMLBM_API size_t ibmlbm_workspace_bytes(const ibmlbm_config* cfg, int32_t n_wings,
                               const ibmlbm_wing* wings);
 

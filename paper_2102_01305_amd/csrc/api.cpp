@@ -136,6 +136,10 @@ int validate_config(const ibmlbm_config* c, std::string& why) {
   // (c_x, c_y) gives the D2Q9 weights, equilibrium, forcing and streaming)
   if (c->nz < 4 && c->bc[4] != IBMLBM_BC_PERIODIC) { why = "nz < 4 needs a periodic z axis"; return IBMLBM_EINVAL; }
   if ((long long)c->nx * c->ny * c->nz > (1LL << 34)) { why = "box too large"; return IBMLBM_EINVAL; }
+  // the kernels index lattice rows (y, z) with 32-bit integers and address a
+  // row's 19 population rows with 32-bit byte offsets
+  if ((long long)c->ny * c->nz >= (1LL << 31)) { why = "ny * nz must be < 2^31"; return IBMLBM_EINVAL; }
+  if (c->nx >= (1 << 24)) { why = "nx must be < 2^24"; return IBMLBM_EINVAL; }
   for (int f = 0; f < 6; ++f) {
     if (c->bc[f] < 0 || c->bc[f] > 5) { snprintf(b, sizeof b, "bc[%d] unknown", f); why = b; return IBMLBM_EINVAL; }
     if (f >= 2 && c->bc[f] >= IBMLBM_BC_VELOCITY) {

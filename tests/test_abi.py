@@ -83,6 +83,20 @@ def test_workspace_bytes_and_validation():
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 1, w) == 0
 
 
+def test_index_ranges_of_the_kernels_are_enforced():
+    """Lattice rows (y, z) are 32-bit indices in the kernels and a row's 19
+    population rows are addressed with 32-bit byte offsets: boxes beyond
+    those ranges are refused before anything is allocated."""
+    L, lib = _lib()
+    bx, _ = _plate()
+    ok = dict(bx, nx=(1 << 24) - 1, ny=4, nz=4)
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(ok)), 0, None) > 0
+    for dims, msg in (((1 << 24, 4, 4), b"nx must be"), ((4, 1 << 16, 1 << 15), b"ny * nz")):
+        bad = dict(bx, nx=dims[0], ny=dims[1], nz=dims[2])
+        assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(bad)), 0, None) == 0
+        assert msg in lib.ibmlbm_last_error(None)
+
+
 def test_fp16_workspace_is_half_the_lattice():
     L, lib = _lib()
     bx, wg = _plate()
