@@ -47,6 +47,10 @@ LATTICE_CASES = [
     ("z_walls", (64, 12, 10), [P, P, P, P, Wl, Wl], 0.66, {}),
     ("zou_he_channel", (70, 18, 10), [ZV, ZP, Wl, Wl, P, P], 0.7, dict(u_in=[0.03, 0.005, 0.002])),
     ("zou_he_periodic", (45, 12, 9), [ZV, ZP, P, P, P, P], 0.6, dict(u_in=[0.02, -0.004, 0.003], rho_out=1.01)),
+    # thin periodic axes: both z neighbours wrap onto the same plane (nz = 2)
+    # or onto the two others (nz = 3), and y wraps at ny = 4
+    ("thin_periodic_nz2", (130, 4, 2), [P] * 6, 0.7, {}),
+    ("thin_nz3_inlet_walls", (66, 5, 3), [V, PR, Wl, Wl, P, P], 0.7, dict(u_in=[0.02, 0.003, 0.001])),
 ]
 
 

@@ -182,6 +182,7 @@ RAGGED = [
      0.7, dict(u_in=[0.03, 0.005, 0])),
     ("inlet_outlet_odd", (131, 9, 7), [WL.VELOCITY, WL.PRESSURE, WL.WALL, WL.WALL, WL.WALL, WL.WALL],
      0.75, dict(u_in=[0.02, 0.0, 0.004])),
+    ("thin_periodic_nz2", (130, 4, 2), [WL.PERIODIC] * 6, 0.7, {}),
 ]
 
 
