@@ -25,6 +25,34 @@ __device__ __forceinline__ bool in_box(const FoilBox& b, int x, int y) {
   return y >= b.y0 && y < b.y0 + b.h && x >= b.x0 && x < b.x0 + b.w;
 }
 
+// du(x) of the IBM correction (Eq. 15): the sum over foils and the 4 span
+// layers within reach of the layer images written by the spread kernel.
+// Returns whether a foil's node box covers the cell.
+__device__ __forceinline__ bool correction(const CollideArgs& a, int x, int y, int z, float& dux,
+                                           float& duy, float& duz) {
+  const Geo& g = a.g;
+  dux = duy = duz = 0.f;
+  bool hit = false;
+  for (int w = 0; w < a.nw; ++w) {
+    const FoilBox& b = a.box[w];
+    if (y < b.y0 || y >= b.y0 + b.h) continue;         // wave-uniform: most rows miss
+    if (!in_box(b, x, y)) continue;
+    const int lx = x - b.x0, ly = y - b.y0;
+    hit = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      int s = z - 2 + k;
+      s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
+      s = s < 0 ? s + g.nz : s;                        // a span of one layer wraps twice
+      const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
+      dux += a.wz[k] * v.x;
+      duy += a.wz[k] * v.y;
+      duz += a.wz[k] * v.z;
+    }
+  }
+  return hit;
+}
+
 // One cell update: pull-streaming, the Zou-He rebuild at the x faces (ZH:
 // the solve has Zou-He faces), moments, optional IBM velocity
 // correction and Guo forcing, BGK relaxation, streaming store of the
@@ -47,6 +75,11 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
     pull19_rows<St>(S, g, x, y, z, f);
   else
     pull19<St, true>(S, g, x, y, z, f);
+  // IBM correction: with Zou-He faces it is fetched while the pull is in
+  // flight (measured faster there), else after the moments
+  float dux = 0.f, duy = 0.f, duz = 0.f;
+  bool hit = false;
+  if (IBM && ZH) hit = correction(a, x, y, z, dux, duy, duz);
   if constexpr (ZH) {
     // Zou-He x faces: rebuild the entering populations at the face lanes
     // (the rule of zou_he, each face's branch on its own so the rest of
@@ -70,27 +103,7 @@ __device__ __forceinline__ float collide_cell(const CollideArgs& a, const typena
   float ux = jx * inv, uy = jy * inv, uz = jz * inv;
   bool forced = FORCE;
   if (IBM) {
-    // du(x) = sum over foils and the 4 span layers within reach of the
-    // layer images written by the spread kernel (Eq. 15)
-    float dux = 0.f, duy = 0.f, duz = 0.f;
-    bool hit = false;
-    for (int w = 0; w < a.nw; ++w) {
-      const FoilBox& b = a.box[w];
-      if (y < b.y0 || y >= b.y0 + b.h) continue;         // wave-uniform: most rows miss
-      if (!in_box(b, x, y)) continue;
-      const int lx = x - b.x0, ly = y - b.y0;
-      hit = true;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        int s = z - 2 + k;
-        s = s < 0 ? s + g.nz : (s >= g.nz ? s - g.nz : s);
-        s = s < 0 ? s + g.nz : s;                        // a span of one layer wraps twice
-        const float4 v = b.corr[((long long)s * b.side + ly) * b.side + lx];
-        dux += a.wz[k] * v.x;
-        duy += a.wz[k] * v.y;
-        duz += a.wz[k] * v.z;
-      }
-    }
+    if (!ZH) hit = correction(a, x, y, z, dux, duy, duz);
     if (hit) {
       ux += dux; uy += duy; uz += duz;                 // Eq. 16
       Fx += 2.0f * srho * dux;                         // Eq. 11 / Eq. 26
