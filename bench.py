@@ -5,7 +5,9 @@ kinematics, delta interpolation, the no-slip solve, spreading, the fused
 collide-stream with Guo forcing and the force/coefficient reduction.  The
 default workload is the clap & fling pair (chord 20, aspect 5) in a
 256x192x192 box at Re = 100, J = 0.01, f = 0.25, FP32 storage, synthetic
-seeded initial noise.  Prints one JSON line.
+seeded initial noise.  Prints one JSON line; the default run adds, under
+"variants", the same measurement for FP16 and BF16 storage, the 512x384x384
+solve (FP32, FP16) and the 256^3 Taylor-Green lattice (FP16).
 
     python bench.py [--steps K] [--warmup W]
                     [--workload cf|large|plate|tgv|fig8_2d|cylinder]
@@ -199,6 +201,69 @@ def serve_bench(budget_bytes, steps, log=None):
     return res
 
 
+def timed_solve(wname, storage, steps, warmup, timing_every):
+    """One solve of workload `wname`: `warmup` untimed steps, then `steps`
+    timed whole steps bracketed by device synchronisation, with the kernels
+    of one step in `timing_every` bracketed by HIP events on the solver's
+    stream.  Returns the workload's name, box, foils, physics, initial
+    fields and the figures of the timed region."""
+    import torch
+
+    from paper_2102_01305_amd.solver import Solver, complete_case
+
+    name, bx, wg, ph = workload(wname)
+    if ph["kind"] == "taylor_green":
+        gb, gw = bx, wg
+        u0, rho0 = ph["u0"], ph["rho0"]
+    else:
+        gb, gw = complete_case(bx, wg, ph)
+        u0, rho0 = initial_velocity(bx, ph, gb["u_in"][0]), None
+    print(f"[bench] {name} storage={storage} tau={gb['tau']:.4f} steps={steps} "
+          f"warmup={warmup}", file=sys.stderr, flush=True)
+    s = Solver(gb, gw, storage=storage, history_steps=max(steps + warmup, 16))
+    s.init_fields(rho=rho0, u=u0)
+    N = bx["nx"] * bx["ny"] * bx["nz"]
+
+    s.step(warmup)
+    torch.cuda.synchronize()
+    s.enable_timing(timing_every)
+    s.read_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tim = s.read_timing()
+    s.enable_timing(0)
+    # sanity: the solve is still finite
+    if gw:
+        f = s.forces(s.step_count - 1, 1)
+        if not np.all(np.isfinite(f)):
+            raise SystemExit("non-finite forces after the timed run")
+    else:
+        if not np.isfinite(s.mass()[1]):
+            raise SystemExit("non-finite mass after the timed run")
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    mlups = N * steps / dt / 1e6
+    bpc = 2 * 19 * (4 if storage == "fp32" else 2)
+    nl = tim["collide_launches"]
+    k6_ms = tim["collide_ms"] / nl if nl else float("nan")
+    cells_per_launch = tim["collide_cells"] / nl if nl else float("nan")
+    achieved = bpc * cells_per_launch / (k6_ms * 1e-3) / 1e9 if nl else float("nan")
+    fig = dict(N=N, dt=dt, mlups=mlups, bpc=bpc, k6_ms=k6_ms, cells_per_launch=cells_per_launch,
+               achieved=achieved, launches=nl, marker_ms=tim["marker_ms"] / max(nl, 1))
+    return name, bx, wg, ph, u0, rho0, fig
+
+
+# The storage formats and the largest workload, measured beside the headline
+# line of the default run: (workload, storage, steps, warmup).
+VARIANTS = (("cf", "fp16", 300, 20), ("cf", "bf16", 300, 20), ("large", "fp32", 50, 5),
+            ("large", "fp16", 50, 5), ("tgv", "fp16", 200, 20))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +281,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=4.0,
                     help="HBM budget of the served sweep (admission limit)")
     ap.add_argument("--serve-steps", type=int, default=1000)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other storages and the 512x384x384 solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -226,52 +293,10 @@ def main():
         copy_calibration()
         return
 
-    import torch
-
-    from paper_2102_01305_amd.solver import Solver, complete_case
-
-    name, bx, wg, ph = workload(args.workload)
-    if ph["kind"] == "taylor_green":
-        gb, gw = bx, wg
-        u0, rho0 = ph["u0"], ph["rho0"]
-    else:
-        gb, gw = complete_case(bx, wg, ph)
-        u0, rho0 = initial_velocity(bx, ph, gb["u_in"][0]), None
-    print(f"[bench] {name} storage={args.storage} tau={gb['tau']:.4f} steps={args.steps} "
-          f"warmup={args.warmup}", file=sys.stderr, flush=True)
-    s = Solver(gb, gw, storage=args.storage, history_steps=max(args.steps + args.warmup, 16))
-    s.init_fields(rho=rho0, u=u0)
-    N = bx["nx"] * bx["ny"] * bx["nz"]
-
-    s.step(args.warmup)
-    torch.cuda.synchronize()
-    # timed region: K whole steps, bracketed by device synchronisation;
-    # collide launches are bracketed by HIP events on the solver's stream
-    s.enable_timing(args.timing_every)
-    s.read_timing()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s.step(args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    tim = s.read_timing()
-    s.enable_timing(0)
-    # sanity: the solve is still finite
-    if gw:
-        f = s.forces(s.step_count - 1, 1)
-        if not np.all(np.isfinite(f)):
-            raise SystemExit("non-finite forces after the timed run")
-    else:
-        if not np.isfinite(s.mass()[1]):
-            raise SystemExit("non-finite mass after the timed run")
-    s.close()
-
-    mlups = N * args.steps / dt / 1e6
-    bpc = 2 * 19 * (4 if args.storage == "fp32" else 2)
-    nl = tim["collide_launches"]
-    k6_ms = tim["collide_ms"] / nl if nl else float("nan")
-    cells_per_launch = tim["collide_cells"] / nl if nl else float("nan")
-    achieved = bpc * cells_per_launch / (k6_ms * 1e-3) / 1e9 if nl else float("nan")
+    name, bx, wg, ph, u0, rho0, fig = timed_solve(args.workload, args.storage, args.steps, args.warmup,
+                                                  args.timing_every)
+    N, dt, mlups, bpc = fig["N"], fig["dt"], fig["mlups"], fig["bpc"]
+    k6_ms, cells_per_launch, achieved = fig["k6_ms"], fig["cells_per_launch"], fig["achieved"]
     traffic = measured_traffic(name, args.storage)
     copy_gbs = copy_bandwidth()
     out = {
@@ -294,11 +319,24 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide", "kernel_ms": round(k6_ms, 5),
                      "bytes_per_cell": bpc, "cells_per_launch": cells_per_launch,
-                     "timed_launches": tim["collide_launches"],
-                     "marker_ms_per_step": round(tim["marker_ms"] / max(tim["collide_launches"], 1), 5),
+                     "timed_launches": fig["launches"],
+                     "marker_ms_per_step": round(fig["marker_ms"], 5),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "hbm_frac_whole_step": round(mlups * 1e6 * bpc / (HBM_PEAK_GBS * 1e9), 4),
     }
+    if not args.no_variants and args.workload == "cf" and args.storage == "fp32":
+        # the same measurement for the 16-bit storages and the largest
+        # single solve, so one run records every headline configuration
+        var = []
+        for wv, sv_, kv, wu in VARIANTS:
+            vn, _, _, _, _, _, vf = timed_solve(wv, sv_, kv, wu, args.timing_every)
+            var.append({"workload": vn, "storage": sv_, "steps": kv, "value": round(vf["mlups"], 1),
+                        "ms_per_step": round(vf["dt"] / kv * 1e3, 5),
+                        "kernel_ms": round(vf["k6_ms"], 5), "achieved": round(vf["achieved"], 1),
+                        "frac": round(vf["achieved"] / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(vn, sv_),
+                        "marker_ms_per_step": round(vf["marker_ms"], 5)})
+        out["variants"] = var
     if not args.no_serve:
         print("[bench] served sweep: 64 requests", file=sys.stderr, flush=True)
         sv = serve_bench(int(args.serve_budget_gib * 2**30), args.serve_steps)
