@@ -14,16 +14,25 @@ equilibrium of the initial fields).  One step n, in the order of Sec. 2.2:
  8. record the forces on every foil (Eq. 26, Sec. 3.7)
 
 F_body is an optional uniform force density used by closed-form tests.
+lattice="c" runs steps 1, 2 and 7 through clattice (the same operations in
+plain C with OpenMP, for long runs on large boxes); the default is lattice.py.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import ibm, lattice
+from . import ibm
 
 
 class Sim:
-    def __init__(self, bx, wings=(), rho0=None, u0=None):
+    def __init__(self, bx, wings=(), rho0=None, u0=None, lattice="numpy"):
+        if lattice == "c":
+            from . import clattice as lat
+        elif lattice == "numpy":
+            from . import lattice as lat
+        else:
+            raise ValueError("lattice must be 'numpy' or 'c'")
+        self.lat = lat
         self.nx, self.ny, self.nz = bx["nx"], bx["ny"], bx["nz"]
         self.bc = list(bx["bc"])
         self.tau = float(bx["tau"])
@@ -38,10 +47,10 @@ class Sim:
         shape = (self.nz, self.ny, self.nx)
         rho = np.ones(shape) if rho0 is None else np.asarray(rho0, np.float64).reshape(shape)
         u = np.zeros((3,) + shape) if u0 is None else np.asarray(u0, np.float64).reshape((3,) + shape)
-        self.S = lattice.equilibrium(rho, u)
+        self.S = self.lat.equilibrium(rho, u)
         self.n = 0
-        self.periodic = [self.bc[0] == lattice.PERIODIC, self.bc[2] == lattice.PERIODIC,
-                         self.bc[4] == lattice.PERIODIC]
+        per = self.lat.PERIODIC
+        self.periodic = [self.bc[0] == per, self.bc[2] == per, self.bc[4] == per]
         self.wings = [dict(w) for w in wings]
         self.refs = []
         self.dA = []
@@ -66,8 +75,8 @@ class Sim:
 
     def prestate(self):
         """Pre-collision f of the next step and its rho, u* (Eq. 2, 9, 11)."""
-        f = lattice.stream(self.S, self.bc, self.u_in, self.rho_out)
-        rho, mom = lattice.moments(f)
+        f = self.lat.stream(self.S, self.bc, self.u_in, self.rho_out)
+        rho, mom = self.lat.moments(f)
         ustar = (mom + 0.5 * self.fbody[:, None, None, None]) / rho
         return f, rho, ustar
 
@@ -109,7 +118,7 @@ class Sim:
                              wts=wts, dA=dA, rho=rho, ustar=ustar)
         u = ustar + du
         F = self.fbody[:, None, None, None] + 2.0 * rho[None] * du
-        self.S = lattice.collide(f, rho, u, F, self.tau)
+        self.S = self.lat.collide(f, rho, u, F, self.tau)
         self.history.append(np.array(rec) if rec else np.zeros((0, 8)))
         self.n += 1
 

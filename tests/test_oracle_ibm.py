@@ -286,3 +286,58 @@ def test_figure_eight_kinematics_closed_form():
     assert alpha(w, 0.0)[0] == pytest.approx(math.pi / 4.0, abs=1e-15)
     assert alpha(w, T / 4.0)[0] == pytest.approx(0.0, abs=1e-14)
     assert ob["tau"] == pytest.approx(3.0 * ph["u_tip"] * ph["chord"] / ph["re"] + 0.5, rel=1e-15)
+
+
+def test_single_marker_moment_closed_form():
+    """Moment about the pivot (Sec. 3.7) of one marker moving with U through
+    fluid at rest: the body force is -(1024/27) U (single-marker solve), so
+    about a pivot at X - r the moment is M_z = r_x F_y - r_y F_x =
+    -(1024/27)(r_x U_y - r_y U_x), and C_M = M_z / (0.5 u_ref^2 S chord)."""
+    X = np.array([[6.3, 5.7, 6.1]])
+    U = np.array([[0.01, -0.02, 0.005]])
+    r = np.array([2.25, -1.5])
+    dA = np.array([0.8])
+    N = 12 ** 3
+    nodes, w = ibm.stencil(X, (12, 12, 12), (False, False, False))
+    M, _ = ibm.system_matrix(nodes, w, dA, N)
+    duB = ibm.solve_dense(M, U) / dA[:, None]
+    u_ref, area, chord = 0.05, 3.0, 2.5
+    f = ibm.wing_forces(np.ones(1), duB.T, dA, X, X[0, :2] - r, dict(sense=1.0, chord=chord), u_ref, area)
+    k = 1024.0 / 27.0
+    mz = -k * (r[0] * U[0, 1] - r[1] * U[0, 0])
+    np.testing.assert_allclose(f[3], mz, rtol=1e-13)
+    np.testing.assert_allclose(f[7], mz / (0.5 * u_ref ** 2 * area * chord), rtol=1e-13)
+
+
+def _translating_foil(pivot_frac, centre):
+    # a foil with an even number of perimeter markers (22), chord along x,
+    # translating with a uniform velocity through fluid at rest (Eq. 20 at
+    # t = 0 with phase -pi/2: the pivot moves at trans_amp * 2 pi / T along
+    # trans_angle); fully periodic box
+    a = 5.0
+    hinge = (centre[0] + a * (2.0 * pivot_frac - 1.0), centre[1])
+    wg = [WL.wing(2 * a, 2.0, hinge, pivot_frac, 0.0, 1.0, WL.ALPHA_CONST, period_steps=400.0,
+                  phase=-math.pi / 2, trans_amp=2.0, trans_angle=0.7, ds=0.95)]
+    bx = WL.box(32, 32, 4, [WL.PERIODIC] * 6, 0.8, u_ref=0.03, area_ref=2 * a * 4)
+    s = Sim(bx, wg)
+    assert s.refs[0].shape[0] == 22
+    s.step()
+    return s.forces()[0, 0], a
+
+
+def test_moment_of_translating_foil_about_centre_and_trailing_edge():
+    """A point-symmetric marker set (ellipse with an even number of markers,
+    centre on a lattice node of a periodic box) translating uniformly from
+    rest has point-symmetric marker forces, so its moment about the centre
+    vanishes while the force does not; about the trailing edge, a = c/2
+    further along the chord, the moment is then M_c - a F_y = -a F_y
+    (moment transfer between two points)."""
+    fc, a = _translating_foil(0.5, (16.0, 16.0))
+    ft, _ = _translating_foil(1.0, (16.0, 16.0))
+    F = np.hypot(fc[0], fc[1])
+    assert F > 1e-3
+    np.testing.assert_allclose(ft[:3], fc[:3], rtol=1e-13)
+    assert abs(fc[3]) <= 1e-12 * a * F
+    np.testing.assert_allclose(ft[3], -a * fc[1], rtol=1e-12)
+    qs = 0.5 * 0.03 ** 2 * (10.0 * 4)
+    np.testing.assert_allclose(ft[7], ft[3] / (qs * 10.0), rtol=1e-13)

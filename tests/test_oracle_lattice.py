@@ -261,3 +261,44 @@ def test_zou_he_uniform_flow_is_a_fixed_point():
         rho, mom = L.moments(f)
         S = L.collide(f, rho, mom / rho, np.zeros((3,) + shape), 0.8)
     assert np.allclose(S, L.equilibrium(np.ones(shape), u), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("backend", ["numpy", "c"])
+def test_inlet_outlet_half_range_mass_flux(backend):
+    """Mass entering through the equilibrium faces (Sec. 2.1), against the
+    half-range moments of the equilibrium, worked out by hand for D3Q19:
+    over the five populations with c_x = +1, sum w_i [1 + 3 c.u + 4.5 (c.u)^2
+    - 1.5 u.u] = (1 + 3 u_x + 3 u_x^2) / 6 for any u_y, u_z, and over c_x = -1
+    it is (1 - 3 u_x + 3 u_x^2) / 6.  So after streaming, the populations
+    entering a velocity-inlet cell sum to rho_b (1 + 3 U + 3 U^2) / 6 with
+    rho_b the density of that boundary cell, and those entering a
+    pressure-outlet cell sum to rho_out (1 - 3 u_b + 3 u_b^2) / 6 with u_b the
+    x velocity of the boundary cell.  The state varies along x only (y, z
+    periodic), with density and velocity different in the neighbouring
+    columns, so a ghost taken from any other cell fails."""
+    lat = L if backend == "numpy" else __import__("oracle.clattice", fromlist=["x"])
+    nz, ny, nx = 3, 4, 7
+    x = np.arange(nx)
+    rho = np.broadcast_to(1.0 + 0.02 * np.sin(1.3 * x + 0.4), (nz, ny, nx)).copy()
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = 0.03 + 0.02 * np.cos(0.9 * x)
+    u[1] = 0.01 * np.sin(0.7 * x)
+    u[2] = -0.015 * np.cos(0.5 * x)
+    rng = np.random.default_rng(8)
+    neq = 1e-3 * rng.standard_normal((19, nx)) * L.W[:, None]
+    # a non-equilibrium part with zero mass and momentum keeps rho, u of S
+    A = np.vstack([np.ones(19), L.C.T.astype(float)])          # (4, 19)
+    neq = neq - A.T @ np.linalg.solve(A @ A.T, A @ neq)
+    S = L.equilibrium(rho, u) + neq[:, None, None, :]
+    rS, mS = L.moments(S)
+    np.testing.assert_allclose(rS, rho, atol=1e-15)
+    U_in, rho_out = 0.045, 1.013
+    f = lat.stream(S, [V, PR, P, P, P, P], [U_in, 0.02, -0.01], rho_out)
+    inl = f[L.C[:, 0] == 1][:, :, :, 0].sum(axis=0)
+    np.testing.assert_allclose(inl, rho[0, 0, 0] * (1 + 3 * U_in + 3 * U_in ** 2) / 6, rtol=1e-14)
+    ub = mS[0, 0, 0, nx - 1] / rS[0, 0, nx - 1]
+    out = f[L.C[:, 0] == -1][:, :, :, nx - 1].sum(axis=0)
+    np.testing.assert_allclose(out, rho_out * (1 - 3 * ub + 3 * ub ** 2) / 6, rtol=1e-14)
+    # and the neighbouring column differs, so the pin separates the cells
+    assert abs(rho[0, 0, 1] - rho[0, 0, 0]) > 1e-3
+    assert abs(mS[0, 0, 0, nx - 2] / rS[0, 0, nx - 2] - ub) > 1e-3
