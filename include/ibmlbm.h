@@ -191,14 +191,29 @@ IBMLBM_API int ibmlbm_set_stream(ibmlbm_t h, void* hip_stream);
 /* Number of steps taken since init_fields (plus step0). */
 IBMLBM_API int64_t ibmlbm_step_count(ibmlbm_t h);
 
-/* Copy force history rows [first, first+count) to out[count][n_wings][8]:
- * Fx, Fy, Fz, Mz (force/moment on the body), CL, CT, CD, CM.  ERANGE if a
- * row is not in the ring. */
+/* Copy force history rows [first, first+count) to out[count][n_wings][8]
+ * (host memory, caller-owned, row-major), the force integration of Sec. 3.7:
+ * the Lagrangian force density f_B = 2 rho_B du_B / dt of each marker (Eq. 26)
+ * times its surface element, summed over the foil, with the sign turned to
+ * give the force on the body; then
+ *   Fx, Fy, Fz  force on the body,
+ *   Mz          its moment about the foil's pivot, sum (X - X_pivot) x f,
+ *   CL          lift = lateral force, counted along -sense * y (outward for a
+ *               mirrored pair), over 0.5 u_ref^2 area_ref (Sec. 3.6),
+ *   CT, CD      thrust -Fx and drag Fx over the same,
+ *   CM          Mz over 0.5 u_ref^2 area_ref chord.
+ * Synchronises the stream.  ERANGE if a row is not in the ring, ESTATE with
+ * no foils, EDIVERGED if a check step saw a non-finite density or a perimeter
+ * system became singular (the rows are still copied). */
 IBMLBM_API int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out);
 
-/* Copy a field of the current state to host float64: RHO (N), U (3N: the
- * velocity u* = (sum c f + F_body/2)/rho of the distributions the next step
- * starts from), FDIST (19N: the post-collision state, canonical order). */
+/* Copy a field of the current state to host float64 (caller-owned, x
+ * fastest): RHO (N: rho = sum_i f_i, Eq. 2), U (3N: the velocity
+ * u* = (sum_i c_i f_i + F_body/2)/rho of Eqs. 2, 9 and 11, of the streamed
+ * distributions the next step starts from, before its IBM correction),
+ * FDIST (19N: the post-collision state f* of Eq. 7, canonical order).
+ * Synchronises the stream; RHO and U use the other state buffer as scratch.
+ * ESTATE before init_fields, EINVAL for an unknown field. */
 IBMLBM_API int ibmlbm_fields(ibmlbm_t h, int32_t which, double* out);
 
 /* Marker data of the last completed step, float64, marker order
@@ -236,6 +251,19 @@ IBMLBM_API const char* ibmlbm_last_error(ibmlbm_t h);
  * period T = 2 Phi chord / U_tip with Phi = 120 degrees. */
 IBMLBM_API int ibmlbm_lattice_params(double Re, double J, double f, double chord, double kappa,
                           double* tau, double* u_inf, double* u_tip, double* period_steps);
+
+/* Fixed foil in a uniform stream (a plate at an angle of attack, Sec. 3.2-3.3
+ * setups; the cylinder of Sec. 3.1): Re = u_inf chord / nu, so
+ * nu = u_inf chord / Re and tau = 3 nu + 1/2 (Eq. 3 in lattice units).  EINVAL
+ * unless Re, u_inf and chord are > 0. */
+IBMLBM_API int ibmlbm_plate_params(double Re, double u_inf, double chord, double* tau);
+
+/* Figure-eight hovering stroke (Sec. 3.2, Eqs. 20-22): Re = U_tip c / nu with
+ * the largest speed of the wing centre U_tip = pi f A0 (Eq. 22).  Given the
+ * lattice tip speed u_tip: nu = u_tip chord / Re, tau = 3 nu + 1/2 (Eq. 3) and
+ * the period 1/f = pi A0 / u_tip steps.  EINVAL unless every input is > 0. */
+IBMLBM_API int ibmlbm_figure_eight_params(double Re, double u_tip, double chord, double a0,
+                                          double* tau, double* period_steps);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,8 @@ SIGNATURES = [
     ("ibmlbm_destroy", C.c_int, [Handle]),
     ("ibmlbm_last_error", C.c_char_p, [Handle]),
     ("ibmlbm_lattice_params", C.c_int, [C.c_double] * 5 + [_dp] * 4),
+    ("ibmlbm_plate_params", C.c_int, [C.c_double] * 3 + [_dp]),
+    ("ibmlbm_figure_eight_params", C.c_int, [C.c_double] * 4 + [_dp] * 2),
 ]
 
 _lib = None

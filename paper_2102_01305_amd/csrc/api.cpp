@@ -36,6 +36,7 @@ struct LatticeLayout {
   size_t N = 0;
   int nxc = 0, nblocks = 0;
   Region fA, fB, mass_part, diag, argtab;
+  size_t state_end = 0;  // bytes of the two states
   size_t end = 0;
 };
 
@@ -49,6 +50,7 @@ struct WingGeom {
   std::vector<double> ref;         // np x 2, relative to the pivot
   double rmax = 0.0;
   int side = 0;                    // pitch of the per-layer node-box images
+  int max_cells = 0;               // largest node box over the motion (cells, with margin)
 };
 
 constexpr int kPwStride = 14;      // doubles per perimeter record (markers.hip)
@@ -68,6 +70,11 @@ struct ibmlbm_s {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  // base of every region other than the two lattice states: the workspace
+  // itself, or this device's static scratch for ibmlbm_create_noalloc
+  char* sb = nullptr;
+  size_t sb_bytes = 0;
+  bool noalloc = false;
   LatticeLayout L;
   Geo geo{};
   Phys phys{};
@@ -121,7 +128,7 @@ int fail(ibmlbm_t h, int code, const char* fmt, ...) {
 
 template <class T>
 T* at(ibmlbm_t h, const Region& r) {
-  return reinterpret_cast<T*>(h->ws + r.off);
+  return reinterpret_cast<T*>(h->sb + r.off);
 }
 
 void* cur_state(ibmlbm_t h) { return h->ws + (h->cur_is_A ? h->L.fA.off : h->L.fB.off); }
@@ -162,7 +169,10 @@ int validate_config(const ibmlbm_config* c, std::string& why) {
   return IBMLBM_OK;
 }
 
-LatticeLayout lattice_layout(const ibmlbm_config* c) {
+// split: the two states alone from offset 0 of the caller's buffer, the
+// other regions from offset 0 of a separate scratch (ibmlbm_create_noalloc);
+// otherwise everything follows on in one workspace.
+LatticeLayout lattice_layout(const ibmlbm_config* c, bool split = false) {
   LatticeLayout L;
   L.es = c->storage == IBMLBM_FP32 ? 4 : 2;
   const int line = 128 / L.es;
@@ -178,6 +188,8 @@ LatticeLayout lattice_layout(const ibmlbm_config* c) {
   const size_t state = L.goff + 2 * (size_t)c->ny * c->nz * 32;
   take(L.fA, state);
   take(L.fB, state);
+  L.state_end = o;
+  if (split) o = 0;
   take(L.mass_part, (size_t)L.nblocks * sizeof(double));
   take(L.diag, 64);
   take(L.argtab, (size_t)kFactorWindow * kArgSlotBytes);
@@ -497,6 +509,33 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
               return IBMLBM_EINVAL;
             }
           }
+    for (int k = 0; k < nw; ++k) {
+      // node box at this pose, grown by 3 cells against poses between samples
+      WingDev d{};
+      node_box(w[k], geo[k], t, c, d);
+      const int bw = std::min(d.bw + 3, geo[k].side), bh = std::min(d.bh + 3, geo[k].side);
+      geo[k].max_cells = std::max(geo[k].max_cells, bw * bh);
+    }
+  }
+  // local memory of the marker kernels: the perimeter factor block holds the
+  // n_p x n_p matrix, the records and a column; the layer block holds the
+  // inverse, the records, the layer's solution, at least one partial spread
+  // image of the largest node box and an 8 KB reduction array (markers.hip)
+  int maxnp = 0, maxcells = 0;
+  for (int k = 0; k < nw; ++k) {
+    maxnp = std::max(maxnp, geo[k].np);
+    maxcells = std::max(maxcells, geo[k].max_cells);
+  }
+  const size_t lds_factor = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 1) * maxnp) * 8;
+  const size_t lds_layer = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192 +
+                           (size_t)maxcells * 12;
+  if (nw > 0 && std::max(lds_factor, lds_layer) > kMaxLds) {
+    snprintf(b, sizeof b,
+             "%d perimeter markers with a node box of up to %d cells need %zu bytes of the layer kernel's "
+             "local memory (limit %zu): reduce the chord or raise ds",
+             maxnp, maxcells, std::max(lds_factor, lds_layer), kMaxLds);
+    why = b;
+    return IBMLBM_EINVAL;
   }
   return IBMLBM_OK;
 }
@@ -608,7 +647,7 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ca.nxc_mul = div_mul(L.nxc, (unsigned long long)L.nblocks * kBlockRows);
   ca.ny_mul = div_mul(c.ny, (unsigned long long)c.ny * c.nz);
   ca.mass_part = at<double>(h, L.mass_part);
-  ca.flags = reinterpret_cast<int*>(h->ws + L.diag.off + 16);
+  ca.flags = reinterpret_cast<int*>(h->sb + L.diag.off + 16);
   void* A = h->ws + L.fA.off;
   void* B = h->ws + L.fB.off;
   ca.src = cur_A ? A : B;
@@ -674,10 +713,10 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
 }
 
 const void* dev_ca(ibmlbm_t h, int slot) {
-  return h->ws + h->L.argtab.off + (size_t)slot * sizeof(CollideArgs);
+  return h->sb + h->L.argtab.off + (size_t)slot * sizeof(CollideArgs);
 }
 const void* dev_ma(ibmlbm_t h, int slot) {
-  return h->ws + h->L.argtab.off + (size_t)kFactorWindow * sizeof(CollideArgs) +
+  return h->sb + h->L.argtab.off + (size_t)kFactorWindow * sizeof(CollideArgs) +
          (size_t)slot * sizeof(MarkerArgs);
 }
 
@@ -691,12 +730,19 @@ int fill_window(ibmlbm_t h, long long s0) {
   for (int k = 0; k < kFactorWindow; ++k)
     step_args(h, s0 + k, h->cur_is_A == ((k & 1) == 0), h->wca[k], h->wma[k]);
   if (h->pin_pending) HIP_TRY(h, hipEventSynchronize(h->pin_ev));
-  char* pin = static_cast<char*>(h->pin);
-  std::memcpy(pin, h->wca.data(), (size_t)kFactorWindow * sizeof(CollideArgs));
-  std::memcpy(pin + (size_t)kFactorWindow * sizeof(CollideArgs), h->wma.data(),
-              (size_t)kFactorWindow * sizeof(MarkerArgs));
-  HIP_TRY(h, hipMemcpyAsync(h->ws + h->L.argtab.off, pin, h->L.argtab.bytes, hipMemcpyHostToDevice,
-                            h->stream));
+  char* dev = h->sb + h->L.argtab.off;
+  const size_t cb = (size_t)kFactorWindow * sizeof(CollideArgs), mb = (size_t)kFactorWindow * sizeof(MarkerArgs);
+  if (h->pin) {
+    char* pin = static_cast<char*>(h->pin);
+    std::memcpy(pin, h->wca.data(), cb);
+    std::memcpy(pin + cb, h->wma.data(), mb);
+    HIP_TRY(h, hipMemcpyAsync(dev, pin, cb + mb, hipMemcpyHostToDevice, h->stream));
+  } else {
+    // no pinned staging (ibmlbm_create_noalloc): straight from the host
+    // copies, which are not touched again before the event below completes
+    HIP_TRY(h, hipMemcpyAsync(dev, h->wca.data(), cb, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(dev + cb, h->wma.data(), mb, hipMemcpyHostToDevice, h->stream));
+  }
   HIP_TRY(h, hipEventRecord(h->pin_ev, h->stream));
   h->pin_pending = true;
   return IBMLBM_OK;
@@ -803,12 +849,64 @@ int run_steps(ibmlbm_t* hs, int n, int steps) {
       if (c.check_interval > 0 && ((s + 1) % c.check_interval == 0))
         HIP_TRY(h, launch_mass_reduce(at<double>(h, h->L.mass_part), h->L.nblocks,
                                       (double)h->L.N,
-                                      reinterpret_cast<double*>(h->ws + h->L.diag.off), s + 1, st));
+                                      reinterpret_cast<double*>(h->sb + h->L.diag.off), s + 1, st));
       h->cur_is_A = !h->cur_is_A;
       h->step = s + 1;
       if (h->nw > 0) h->markers_valid = true;
     }
   }
+  return IBMLBM_OK;
+}
+
+// Handle of a solve.  noalloc: the caller's buffer holds the two lattice
+// states only; every other region comes from this device's static scratch
+// (scratch.hip), and no pinned staging buffer is made.
+int create_handle(const ibmlbm_config* cfg, void* dev_buf, size_t bytes, void* hip_stream, ibmlbm_t* out,
+                  bool noalloc) {
+  if (!out) return fail(nullptr, IBMLBM_EINVAL, "null output handle");
+  *out = nullptr;
+  std::string why;
+  int rc = validate_config(cfg, why);
+  if (rc) return fail(nullptr, rc, "%s", why.c_str());
+  if (!dev_buf) return fail(nullptr, IBMLBM_EINVAL, "null workspace");
+  if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(nullptr, IBMLBM_EINVAL, "workspace must be 256-byte aligned");
+  LatticeLayout L = lattice_layout(cfg, noalloc);
+  const size_t need = noalloc ? L.state_end : L.end;
+  if (bytes < need) return fail(nullptr, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, need);
+  char* sb = static_cast<char*>(dev_buf);
+  size_t sb_bytes = bytes;
+  ibmlbm_t h = new ibmlbm_s();
+  h->cfg = *cfg;
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->ws = static_cast<char*>(dev_buf);
+  h->ws_bytes = bytes;
+  h->sb = sb;
+  h->sb_bytes = sb_bytes;
+  h->noalloc = noalloc;
+  h->L = L;
+  h->geo.nx = cfg->nx;
+  h->geo.ny = cfg->ny;
+  h->geo.nz = cfg->nz;
+  h->geo.px = L.px;
+  h->geo.ps = L.ps;
+  h->geo.goff = (long long)L.goff;
+  h->geo.yper = cfg->bc[2] == IBMLBM_BC_PERIODIC;
+  h->geo.zper = cfg->bc[4] == IBMLBM_BC_PERIODIC;
+  h->geo.bclo = cfg->bc[0];
+  h->geo.bchi = cfg->bc[1];
+  fill_phys(h);
+  // mass, step and flags start at zero (the static scratch keeps the last
+  // solve's contents)
+  hipError_t e = hipMemsetAsync(h->sb + L.diag.off, 0, L.diag.bytes, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && !noalloc) e = hipHostMalloc(&h->pin, L.argtab.bytes, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    int r = fail(nullptr, IBMLBM_EDEVICE, "create failed: %s", hipGetErrorString(e));
+    ibmlbm_destroy(h);
+    return r;
+  }
+  *out = h;
   return IBMLBM_OK;
 }
 
@@ -829,43 +927,7 @@ size_t ibmlbm_workspace_bytes(const ibmlbm_config* cfg, int32_t n_wings, const i
 
 int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
                   ibmlbm_t* out) {
-  if (!out) return fail(nullptr, IBMLBM_EINVAL, "null output handle");
-  *out = nullptr;
-  std::string why;
-  int rc = validate_config(cfg, why);
-  if (rc) return fail(nullptr, rc, "%s", why.c_str());
-  if (!dev_workspace) return fail(nullptr, IBMLBM_EINVAL, "null workspace");
-  if (reinterpret_cast<uintptr_t>(dev_workspace) % 256) return fail(nullptr, IBMLBM_EINVAL, "workspace must be 256-byte aligned");
-  LatticeLayout L = lattice_layout(cfg);
-  if (bytes < L.end) return fail(nullptr, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, L.end);
-  ibmlbm_t h = new ibmlbm_s();
-  h->cfg = *cfg;
-  h->stream = static_cast<hipStream_t>(hip_stream);
-  h->ws = static_cast<char*>(dev_workspace);
-  h->ws_bytes = bytes;
-  h->L = L;
-  h->geo.nx = cfg->nx;
-  h->geo.ny = cfg->ny;
-  h->geo.nz = cfg->nz;
-  h->geo.px = L.px;
-  h->geo.ps = L.ps;
-  h->geo.goff = (long long)L.goff;
-  h->geo.yper = cfg->bc[2] == IBMLBM_BC_PERIODIC;
-  h->geo.zper = cfg->bc[4] == IBMLBM_BC_PERIODIC;
-  h->geo.bclo = cfg->bc[0];
-  h->geo.bchi = cfg->bc[1];
-  fill_phys(h);
-  hipError_t e = hipMemsetAsync(h->ws + L.diag.off, 0, L.diag.bytes, h->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-  if (e == hipSuccess) e = hipHostMalloc(&h->pin, L.argtab.bytes, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    int r = fail(nullptr, IBMLBM_EDEVICE, "create failed: %s", hipGetErrorString(e));
-    ibmlbm_destroy(h);
-    return r;
-  }
-  *out = h;
-  return IBMLBM_OK;
+  return create_handle(cfg, dev_workspace, bytes, hip_stream, out, false);
 }
 
 int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const double* fdist, int64_t step0) {
@@ -906,7 +968,7 @@ int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const dou
     HIP_TRY(h, hipStreamSynchronize(h->stream));
   } else {
     // stage FP64 rho and u in the other state buffer (free between steps)
-    double* stage = at<double>(h, L.fB);
+    double* stage = reinterpret_cast<double*>(h->ws + L.fB.off);
     if ((rho ? N : 0) * 8 + (u ? 3 * N : 0) * 8 > L.fB.bytes)
       return fail(h, IBMLBM_ENOMEM, "staging area too small");
     double* drho = rho ? stage : nullptr;
@@ -932,8 +994,12 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
   int rc = check_wings(h->cfg, n_wings, wings, geo, why);
   if (rc) return fail(h, rc, "%s", why.c_str());
   MarkerLayout M = marker_layout(h->cfg, n_wings, geo, h->L.end);
-  if (n_wings > 0 && M.end > h->ws_bytes)
+  if (n_wings > 0 && M.end > h->sb_bytes) {
+    if (h->noalloc)
+      return fail(h, IBMLBM_ENOMEM, "the markers need %zu bytes of scratch, beyond the static scratch of %zu bytes",
+                  M.end, h->sb_bytes);
     return fail(h, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed for the markers", h->ws_bytes, M.end);
+  }
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   h->nw = n_wings;
   h->geom = geo;
@@ -983,9 +1049,9 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     pwoff += kPwStride * d.np;
     loff += d.ns;
   }
-  HIP_TRY(h, hipMemcpyAsync(h->ws + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemcpyAsync(h->ws + M.G.off, G.data(), G.size() * 8, hipMemcpyHostToDevice, h->stream));
-  HIP_TRY(h, hipMemsetAsync(h->ws + M.hist.off, 0, M.hist.bytes, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->sb + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemcpyAsync(h->sb + M.G.off, G.data(), G.size() * 8, hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(h, hipMemsetAsync(h->sb + M.hist.off, 0, M.hist.bytes, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   return IBMLBM_OK;
 }
@@ -1025,7 +1091,7 @@ int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out) {
                 (long long)h->step);
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   int flags = 0;
-  HIP_TRY(h, hipMemcpy(&flags, h->ws + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&flags, h->sb + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
   const size_t row = (size_t)h->nw * 8;
   const double* hist = at<double>(h, h->M.hist);
   // the rows form at most two contiguous runs of the ring
@@ -1114,7 +1180,7 @@ int ibmlbm_markers(ibmlbm_t h, int32_t which, double* out) {
     default: return fail(h, IBMLBM_EINVAL, "unknown marker field %d", which);
   }
   HIP_TRY(h, hipStreamSynchronize(h->stream));
-  HIP_TRY(h, hipMemcpy(out, h->ws + r->off, count * 8, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(out, h->sb + r->off, count * 8, hipMemcpyDeviceToHost));
   return IBMLBM_OK;
 }
 
@@ -1123,8 +1189,8 @@ int ibmlbm_mass(ibmlbm_t h, int64_t* step, double* mass) {
   HIP_TRY(h, hipStreamSynchronize(h->stream));
   double d[2];
   int flags = 0;
-  HIP_TRY(h, hipMemcpy(d, h->ws + h->L.diag.off, 16, hipMemcpyDeviceToHost));
-  HIP_TRY(h, hipMemcpy(&flags, h->ws + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(d, h->sb + h->L.diag.off, 16, hipMemcpyDeviceToHost));
+  HIP_TRY(h, hipMemcpy(&flags, h->sb + h->L.diag.off + 16, 4, hipMemcpyDeviceToHost));
   *mass = d[0];
   *step = d[1] > 0.0 ? (int64_t)d[1] : -1;
   if (flags & 1) return fail(h, IBMLBM_EDIVERGED, "non-finite density seen on a check step");
@@ -1195,6 +1261,24 @@ int ibmlbm_lattice_params(double Re, double J, double f, double chord, double ka
   if (u_inf) *u_inf = J * ut;
   if (u_tip) *u_tip = ut;
   if (period_steps) *period_steps = 2.0 * Phi * chord / ut;
+  return IBMLBM_OK;
+}
+
+int ibmlbm_plate_params(double Re, double u_inf, double chord, double* tau) {
+  if (!(Re > 0.0) || !(u_inf > 0.0) || !(chord > 0.0))
+    return fail(nullptr, IBMLBM_EINVAL, "Re, u_inf and chord must be > 0");
+  const double nu = u_inf * chord / Re;
+  if (tau) *tau = 3.0 * nu + 0.5;
+  return IBMLBM_OK;
+}
+
+int ibmlbm_figure_eight_params(double Re, double u_tip, double chord, double a0, double* tau,
+                               double* period_steps) {
+  if (!(Re > 0.0) || !(u_tip > 0.0) || !(chord > 0.0) || !(a0 > 0.0))
+    return fail(nullptr, IBMLBM_EINVAL, "Re, u_tip, chord and A0 must be > 0");
+  const double nu = u_tip * chord / Re;
+  if (tau) *tau = 3.0 * nu + 0.5;
+  if (period_steps) *period_steps = M_PI * a0 / u_tip;
   return IBMLBM_OK;
 }
 

@@ -188,17 +188,10 @@ __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, in
 //    outputs from a sliding window of G over one part of the s2 range; the
 //    parts are added in a fixed order.  T is written layer-major.
 // One block holds every layer of its marker, so B never leaves the block.
-__host__ __device__ inline int span_parts(int ns, int threads) {
+__host__ __device__ inline int parts_at(int ns, int threads) {
   const int groups = (ns + 3) / 4;                   // threads per part
   const int parts = threads / groups;
   return parts < 1 ? 1 : (parts > 8 ? 8 : parts);
-}
-
-// Threads of an interp_span block: 512 (more parts of the span range in
-// parallel) where its LDS fits, else 256.
-__host__ __device__ inline size_t interp_span_lds(int ns, int threads);
-__host__ __device__ inline int span_threads(int ns) {
-  return interp_span_lds(ns, 512) <= 150 * 1024 ? 512 : 256;
 }
 
 // LDS of a block: G (2 ns), B (3 ns), partial sums (parts x 3 ns), the xy
@@ -208,9 +201,19 @@ __host__ __device__ inline size_t interp_span_doubles(int ns, int parts) {
   const size_t d = (size_t)(9 + 3 * parts) * ns + kPw;
   return (d + 1) / 2 * 2;
 }
-__host__ __device__ inline size_t interp_span_lds(int ns, int threads) {
-  return interp_span_doubles(ns, span_parts(ns, threads)) * sizeof(double) + 16 * (size_t)ns * 16;
+__host__ __device__ inline size_t lds_at(int ns, int threads) {
+  return interp_span_doubles(ns, parts_at(ns, threads)) * sizeof(double) + 16 * (size_t)ns * 16;
 }
+
+// Threads of an interp_span block for a span of ns layers: 512 (more parts
+// of the span range in parallel) where its LDS fits, else 256.
+__host__ __device__ inline int span_threads(int ns) { return lds_at(ns, 512) <= 150 * 1024 ? 512 : 256; }
+
+// Parts of the span range and LDS of a block: fixed by ns alone, so a
+// solve sums its span solve in the same order whatever block size a grouped
+// launch runs it with (a smaller block takes the parts in turns).
+__host__ __device__ inline int span_parts(int ns) { return parts_at(ns, span_threads(ns)); }
+__host__ __device__ inline size_t interp_span_lds(int ns) { return lds_at(ns, span_threads(ns)); }
 
 __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
@@ -222,7 +225,7 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
   const WingDev& w = a.w[wi];
   const int ns = w.ns, n = w.np;
   const int groups = (ns + 3) / 4;
-  const int parts = span_parts(ns, (int)blockDim.x);
+  const int parts = span_parts(ns);
   const int bd = (int)blockDim.x;
   double* G = lds;              // 2 * ns: G repeated so that G[d + ns] = G[d]
   double* Bc = G + 2 * ns;      // 3 * ns
@@ -299,8 +302,10 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
     }
   }
   __syncthreads();
-  const int part = threadIdx.x / groups, t = threadIdx.x - part * groups;
-  if (part < parts) {
+  // parts in turns of bd / groups (>= 1: ns <= 1024 is checked on the host)
+  const int t = (int)threadIdx.x % groups;
+  for (int part = (int)threadIdx.x / groups; part < parts && (int)threadIdx.x < (bd / groups) * groups;
+       part += bd / groups) {
     const int lo = part * ns / parts, hi = (part + 1) * ns / parts;
     for (int s0 = 4 * t; s0 < ns; s0 += 4 * groups) {
       double acc[4][3];
@@ -438,7 +443,7 @@ __global__ void __launch_bounds__(256) k_layer(Group gr) {
   layer_block(*a, lb);
 }
 
-size_t marker_span_lds(int ns) { return interp_span_lds(ns, span_threads(ns)); }
+size_t marker_span_lds(int ns) { return interp_span_lds(ns); }
 
 static hipError_t raise_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -490,7 +495,7 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
   int thr = 512;
   for (int j = 0; j < n; ++j) thr = span_threads(host[j]->g.nz) < thr ? span_threads(host[j]->g.nz) : thr;
   for (int j = 0; j < n; ++j) {
-    const size_t ls = interp_span_lds(host[j]->g.nz, thr);
+    const size_t ls = interp_span_lds(host[j]->g.nz);
     lds_s = ls > lds_s ? ls : lds_s;
   }
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);

@@ -6,7 +6,6 @@ supplies the device workspace (one uint8 tensor) and the HIP stream.
 from __future__ import annotations
 
 import ctypes as C
-import math
 
 import numpy as np
 
@@ -24,14 +23,29 @@ def lattice_params(re, j, f, chord, kappa=0.2):
     return dict(tau=tau, u_inf=u_inf, u_tip=u_tip, period_steps=period)
 
 
+def plate_params(re, u_inf, chord):
+    """Fixed foil in a uniform stream to lattice units through the library."""
+    lib = L.load()
+    tau = C.c_double()
+    L.check(lib.ibmlbm_plate_params(re, u_inf, chord, C.byref(tau)))
+    return dict(tau=tau.value)
+
+
+def figure_eight_params(re, u_tip, chord, a0):
+    """Figure-eight stroke to lattice units through the library."""
+    lib = L.load()
+    tau, period = C.c_double(), C.c_double()
+    L.check(lib.ibmlbm_figure_eight_params(re, u_tip, chord, a0, C.byref(tau), C.byref(period)))
+    return dict(tau=tau.value, period_steps=period.value)
+
+
 def complete_case(bx, wings, phys):
     """Fill tau, inlet velocity, reference velocity and periods of a workload
     description using the library's own parameter mapping."""
     bx = dict(bx)
     wings = [dict(w) for w in wings]
     if phys["kind"] == "plate":
-        nu = phys["u_inf"] * phys["chord"] / phys["re"]
-        bx["tau"] = 3.0 * nu + 0.5
+        bx["tau"] = plate_params(phys["re"], phys["u_inf"], phys["chord"])["tau"]
         for w in wings:
             if w.get("period_steps") is None:
                 w["period_steps"] = 1.0
@@ -43,12 +57,11 @@ def complete_case(bx, wings, phys):
         for w in wings:
             w["period_steps"] = p["period_steps"]
     elif phys["kind"] == "figure_eight":
-        # Re = U_tip c / nu, U_tip = pi f A0 (Eq. 22): period pi A0 / U_tip
-        nu = phys["u_tip"] * phys["chord"] / phys["re"]
-        bx["tau"] = 3.0 * nu + 0.5
+        p = figure_eight_params(phys["re"], phys["u_tip"], phys["chord"], phys["a0"])
+        bx["tau"] = p["tau"]
         bx["u_ref"] = phys["u_tip"]
         for w in wings:
-            w["period_steps"] = math.pi * phys["a0"] / phys["u_tip"]
+            w["period_steps"] = p["period_steps"]
     else:
         raise ValueError(phys["kind"])
     return bx, wings
@@ -116,10 +129,9 @@ class Solver:
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        self.h = L.Handle()
-        L.check(self.lib.ibmlbm_create(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()),
-                                       self.nbytes, C.c_void_p(self.stream.cuda_stream),
-                                       C.byref(self.h)))
+            self.h = L.Handle()
+            L.check(self.lib.ibmlbm_create(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()), self.nbytes,
+                           C.c_void_p(self.stream.cuda_stream), C.byref(self.h)))
         if nw:
             L.check(self.lib.ibmlbm_set_kinematics(self.h, nw, self._wings), self.h)
         self.N = self.cfg.nx * self.cfg.ny * self.cfg.nz

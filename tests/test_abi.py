@@ -129,6 +129,41 @@ def test_lattice_params_agree_with_the_paper_mapping():
     assert lib.ibmlbm_lattice_params(-1.0, 0.0, 0.25, 20.0, 0.2, C.byref(t), None, None, None) == L.EINVAL
 
 
+def test_plate_and_figure_eight_params():
+    """Eq. 3 with Re = U c / nu: the plate workload (Re 100, u 0.02, c 10)
+    has nu = 0.002 and tau = 0.506; the figure-eight stroke (Eq. 22, Re 75,
+    U_tip 0.05, c 15, A0 = 2.5 c) has nu = 0.01, tau = 0.53 and the period
+    pi A0 / U_tip = 2356.19 steps."""
+    from paper_2102_01305_amd.solver import figure_eight_params, plate_params
+    assert abs(plate_params(100.0, 0.02, 10.0)["tau"] - 0.506) < 1e-15
+    p = figure_eight_params(75.0, 0.05, 15.0, 37.5)
+    assert abs(p["tau"] - 0.53) < 1e-15
+    assert abs(p["period_steps"] - math.pi * 37.5 / 0.05) < 1e-9
+    L, lib = _lib()
+    t = C.c_double()
+    assert lib.ibmlbm_plate_params(100.0, 0.0, 10.0, C.byref(t)) == L.EINVAL
+    assert lib.ibmlbm_figure_eight_params(75.0, 0.05, 15.0, -1.0, C.byref(t), None) == L.EINVAL
+
+
+@pytest.mark.parametrize("chord,accepted", [(50.0, True), (60.0, False)])
+def test_marker_local_memory_limit(chord, accepted):
+    """The layer kernel keeps the perimeter inverse (n_p^2 doubles) and a
+    partial spread image of the foil's node box in local memory: a clap &
+    fling pair at aspect ratio 5 with chord 50 (105 perimeter markers) fits
+    the 160 KB of a workgroup, chord 60 (126 markers) does not and is
+    refused at configuration time, not at the first step."""
+    L, lib = _lib()
+    from paper_2102_01305_amd.solver import complete_case, make_wings
+    bx, wg, ph = WL.clap_fling_case(nx=400, ny=320, nz=8, chord=chord, re=100.0, j=0.01, f=0.25)
+    gb, gw = complete_case(bx, wg, ph)
+    n = lib.ibmlbm_workspace_bytes(C.byref(_cfg(gb)), len(gw), make_wings(gw))
+    if accepted:
+        assert n > 0
+    else:
+        assert n == 0
+        assert b"local memory" in lib.ibmlbm_last_error(None)
+
+
 def test_solver_refuses_without_gpu():
     import torch
     if torch.cuda.is_available():

@@ -2,8 +2,11 @@
 
 Bars: after 200 steps of the 64x32x32 plate workload, the L2-relative error
 of u over all cells is <= 1e-5 and every step's lift coefficient is within
-1e-3 of max|C_L| of the oracle.  Lattice-only cases use the same L2 bar.
-Every case prints its name, shape and seed before touching the GPU.
+1e-3 of max|C_L| of the oracle; the same per-step rule holds for the moment
+about the pivot M_z, C_T, C_D and C_M, and u on the cells the markers'
+kernel supports cover is held element by element to 1e-5 of its largest
+value there.  Lattice-only cases use the same L2 bar.  Every case prints its
+name, shape and seed before touching the GPU.
 """
 import math
 import sys
@@ -12,7 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import clap_fling, gpu_solver, l2rel, oracle_sim, plate
+from tests.helpers import clap_fling, coeff_errors, gpu_solver, l2rel, node_box_error, oracle_sim, plate
 
 pytestmark = pytest.mark.gpu
 
@@ -90,14 +93,12 @@ def test_plate_200_steps(seed):
     err = l2rel(u_g, u_o)
     print("L2 rel u", err)
     assert err <= 1e-5
-    fg = gpu.forces(0, 200)
-    fo = ora.forces()
-    cl_g, cl_o = fg[:, 0, 4], fo[:, 0, 4]
-    dcl = np.abs(cl_g - cl_o).max() / np.abs(cl_o).max()
-    print("max |dCL| / max|CL|", dcl)
-    assert dcl <= 1e-3
-    for k in (5, 6):   # drag and thrust histories too
-        assert np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max() <= 1e-3
+    eb = node_box_error(u_g, u_o, ora.last["nodes"])
+    print("node-box max |du| / max|u|", eb)
+    assert eb <= 1e-5
+    d = coeff_errors(gpu.forces(0, 200), ora.forces())
+    print("coefficients max rel", d)
+    assert max(d.values()) <= 1e-3
     gpu.close()
 
 
@@ -183,23 +184,32 @@ def test_clap_fling_small_parity():
     gpu.step(60)
     ora.run(60)
     rho_o, u_o = ora.fields()
-    assert l2rel(gpu.fields("u"), u_o) <= 1e-5
-    fg = gpu.forces(150, 60)
-    fo = ora.forces()
-    for w in range(2):
-        assert np.abs(fg[:, w, 4] - fo[:, w, 4]).max() <= 1e-3 * np.abs(fo[:, w, 4]).max()
+    u_g = gpu.fields("u")
+    assert l2rel(u_g, u_o) <= 1e-5
+    eb = node_box_error(u_g, u_o, ora.last["nodes"])
+    d = coeff_errors(gpu.forces(150, 60), ora.forces())
+    print("node-box", eb, "coefficients max rel", d)
+    assert eb <= 1e-5
+    assert max(d.values()) <= 1e-3
     gpu.close()
 
 
 def test_mirror_symmetry_gpu():
+    """Started at rest (plus the free stream) from mid-stroke, the mirrored
+    pair stays mirror-symmetric: F_x equal, F_y and M_z opposite for the two
+    foils at every step, to FP32 rounding (measured about 1e-8 of the force
+    scale)."""
     _say("mirror symmetry, clap & fling 64x48x8")
     bx, wg, ph, u0 = clap_fling(seed=0, nx=64, ny=48, nz=8, chord=8.0, re=100.0, j=0.5, f=0.25)
     gpu = gpu_solver(bx, wg, ph, u0=np.zeros_like(u0), step0=37)
     gpu.step(20)
     h = gpu.forces(37, 20)
     scale = np.abs(h[:, :, :2]).max()
-    assert np.abs(h[:, 0, 0] - h[:, 1, 0]).max() <= 1e-4 * scale
-    assert np.abs(h[:, 0, 1] + h[:, 1, 1]).max() <= 1e-4 * scale
+    mscale = np.abs(h[:, :, 3]).max()
+    e = (np.abs(h[:, 0, 0] - h[:, 1, 0]).max() / scale, np.abs(h[:, 0, 1] + h[:, 1, 1]).max() / scale,
+         np.abs(h[:, 0, 3] + h[:, 1, 3]).max() / mscale)
+    print("mirror Fx, Fy, Mz", e)
+    assert max(e) <= 1e-6
     gpu.close()
 
 
@@ -233,15 +243,14 @@ def test_figure_eight_parity():
     gpu.step(80)
     ora.run(80)
     rho_o, u_o = ora.fields()
-    err = l2rel(gpu.fields("u"), u_o)
-    print("L2 rel u", err)
+    u_g = gpu.fields("u")
+    err = l2rel(u_g, u_o)
+    eb = node_box_error(u_g, u_o, ora.last["nodes"])
+    d = coeff_errors(gpu.forces(t0, 80), ora.forces())
+    print("L2 rel u", err, "node-box", eb, "coefficients max rel", d)
     assert err <= 1e-5
-    fg = gpu.forces(t0, 80)
-    fo = ora.forces()
-    for k in (4, 5):
-        d = np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max()
-        print("coefficient", k, "max rel", d)
-        assert d <= 1e-3
+    assert eb <= 1e-5
+    assert max(d.values()) <= 1e-3
     gpu.close()
 
 
@@ -258,13 +267,12 @@ def test_cylinder_zou_he_parity():
     gpu.step(150)
     ora.run(150)
     rho_o, u_o = ora.fields()
-    err = l2rel(gpu.fields("u"), u_o)
-    print("L2 rel u", err)
+    u_g = gpu.fields("u")
+    err = l2rel(u_g, u_o)
+    eb = node_box_error(u_g, u_o, ora.last["nodes"])
+    d = coeff_errors(gpu.forces(0, 150), ora.forces())
+    print("L2 rel u", err, "node-box", eb, "coefficients max rel", d)
     assert err <= 1e-5
-    fg = gpu.forces(0, 150)
-    fo = ora.forces()
-    for k in (4, 6):
-        d = np.abs(fg[:, 0, k] - fo[:, 0, k]).max() / np.abs(fo[:, 0, k]).max()
-        print("coefficient", k, "max rel", d)
-        assert d <= 1e-3
+    assert eb <= 1e-5
+    assert max(d.values()) <= 1e-3
     gpu.close()

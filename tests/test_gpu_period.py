@@ -2,8 +2,9 @@
 Eq. 23 read as |sin|), 64x48x8 with c = 8 (T = 671 steps at f = 0.25):
 the lift and thrust histories of both foils against the FP64 oracle, for
 FP32, FP16 and BF16 storage and for the request served in a mixed batch.
-Bar: every step within 1e-3 of max|C| (FP32, FP16, served); BF16 is held
-to its own 3e-2 (its lift error is stated per step in the report line)."""
+Bar: every step within 1e-3 of max|C| for every history column (M_z, C_L,
+C_T, C_D, C_M; FP32, FP16, served); BF16 is held to its own 2.5e-3, about
+three times its largest measured error (7.9e-4, C_T)."""
 import math
 import sys
 
@@ -11,7 +12,7 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import clap_fling, gpu_solver, oracle_sim
+from tests.helpers import clap_fling, coeff_errors, gpu_solver, oracle_sim
 
 pytestmark = pytest.mark.gpu
 
@@ -40,14 +41,10 @@ def _oracle():
 
 
 def _errors(fg, fo):
-    out = {}
-    for k, name in ((4, "cl"), (5, "ct")):
-        out[name] = max(np.abs(fg[:, w, k] - fo[:, w, k]).max() / np.abs(fo[:, w, k]).max()
-                        for w in range(fo.shape[1]))
-    return out
+    return coeff_errors(fg, fo)
 
 
-BAR = {"fp32": 1e-3, "fp16": 1e-3, "bf16": 3e-2}
+BAR = {"fp32": 1e-3, "fp16": 1e-3, "bf16": 2.5e-3}
 
 
 @pytest.mark.parametrize("storage", ["fp32", "fp16", "bf16"])
@@ -60,9 +57,8 @@ def test_full_period(storage):
     fg = gpu.forces(0, n)
     gpu.close()
     e = _errors(fg, _oracle())
-    print(f"[period] {storage} max|dCL|/max|CL| {e['cl']:.3e} max|dCT|/max|CT| {e['ct']:.3e}", flush=True)
-    assert e["cl"] <= BAR[storage]
-    assert e["ct"] <= BAR[storage]
+    print(f"[period] {storage} max|dC|/max|C| {e}", flush=True)
+    assert max(e.values()) <= BAR[storage]
 
 
 def test_full_period_served():
@@ -88,6 +84,5 @@ def test_full_period_served():
     assert all(r.error is None for r in res)
     assert max(srv.batch_sizes) == 3
     e = _errors(res[0].forces, _oracle())
-    print(f"[period] served max|dCL|/max|CL| {e['cl']:.3e} max|dCT|/max|CT| {e['ct']:.3e}", flush=True)
-    assert e["cl"] <= 1e-3
-    assert e["ct"] <= 1e-3
+    print(f"[period] served max|dC|/max|C| {e}", flush=True)
+    assert max(e.values()) <= 1e-3

@@ -15,20 +15,30 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import clap_fling, gpu_solver, l2rel, oracle_sim, plate
+from tests.helpers import clap_fling, coeff_errors, gpu_solver, l2rel, oracle_sim, plate
 
 pytestmark = pytest.mark.gpu
 
 # Bars per storage.  A stored deviation carries a relative rounding error of
 # 2^-12 (FP16, 11-bit significand) or 2^-9 (BF16, 8-bit); the velocity error
 # it drives stays of that order times the few-step memory of the relaxation.
-# The FP16 lift bar is the 1e-3 of max|C_L| that FP32 meets; BF16 gets a bar
-# 8x the FP16 one for u and reports its lift error against a 3e-2 bar.
+# The FP16 bar of the force coefficients (C_L, C_T, C_D) is the 1e-3 of
+# max|C| that FP32 meets.  The moment about the pivot (M_z, C_M) of the
+# centre-pivoted plate is a small difference of the lift acting ahead of and
+# behind the pivot, so the same storage rounding is a larger share of it:
+# FP16 reaches 1.0e-3 there and is held to 3e-3.  BF16 does not meet 1e-3
+# on every case (its lift error reaches 1.4e-3), so it is held to bars about
+# three times its largest measured errors.
 BARS = {
-    "fp32": dict(u=1e-5, cl=1e-3, tg=1e-5),
-    "fp16": dict(u=1e-3, cl=1e-3, tg=1e-3),
-    "bf16": dict(u=8e-3, cl=3e-2, tg=8e-3),
+    "fp32": dict(u=1e-5, cl=1e-3, cm=1e-3, tg=1e-5),
+    "fp16": dict(u=1e-3, cl=1e-3, cm=3e-3, tg=1e-3),
+    "bf16": dict(u=1.2e-2, cl=5e-3, cm=1.5e-2, tg=8e-3),
 }
+
+
+def _check_coefficients(d, b):
+    assert max(d[k] for k in ("cl", "ct", "cd")) <= b["cl"]
+    assert max(d[k] for k in ("mz", "cm")) <= b["cm"]
 _ORACLE = {}
 
 
@@ -65,13 +75,11 @@ def test_storage_plate_200_steps(storage):
     rho_o, u_o, fo = _plate_oracle()
     e_u = l2rel(u_g, u_o)
     e_rho = float(np.linalg.norm(rho_g - rho_o) / np.linalg.norm(rho_o - 1.0))
-    d = {k: np.abs(fg[:, 0, c] - fo[:, 0, c]).max() / np.abs(fo[:, 0, c]).max()
-         for k, c in (("cl", 4), ("ct", 5), ("cd", 6))}
+    d = coeff_errors(fg, fo)
     _report(storage, "plate200", l2_u=e_u, rho=e_rho, **d)
     b = BARS[storage]
     assert e_u <= b["u"]
-    assert d["cl"] <= b["cl"]
-    assert d["cd"] <= b["cl"]
+    _check_coefficients(d, b)
 
 
 def _cf_oracle(j):
@@ -100,12 +108,11 @@ def test_storage_clap_fling_small(storage, j):
     gpu.close()
     u_o, fo = _cf_oracle(j)
     e_u = l2rel(u_g, u_o)
-    dcl = max(np.abs(fg[:, w, 4] - fo[:, w, 4]).max() / np.abs(fo[:, w, 4]).max() for w in range(2))
-    dct = max(np.abs(fg[:, w, 5] - fo[:, w, 5]).max() / np.abs(fo[:, w, 5]).max() for w in range(2))
-    _report(storage, f"clapfling_J{j}", l2_u=e_u, cl=dcl, ct=dct)
+    d = coeff_errors(fg, fo)
+    _report(storage, f"clapfling_J{j}", l2_u=e_u, **d)
     b = BARS[storage]
     assert e_u <= b["u"]
-    assert dcl <= b["cl"]
+    _check_coefficients(d, b)
 
 
 def _tg_oracle(n, steps):
