@@ -152,6 +152,24 @@ IBMLBM_API int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size
 IBMLBM_API int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u,
                        const double* fdist, int64_t step0);
 
+/* ibmlbm_create for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * dev_state (256-byte aligned, caller-owned) holds only the two lattice
+ * states; bytes >= ibmlbm_workspace_bytes(cfg, 0, NULL) is enough.  Every
+ * other region of the solve (launch arguments, mass partials and flags,
+ * marker data, node-box images, the force-history ring) lives in a static
+ * device array of the library, 64 MiB per device, held from the first such
+ * call on a device until the process ends; no pinned host buffer is made and
+ * nothing is allocated with hipMalloc, hipHostMalloc or any other allocator.
+ * The device current at the call must be the stream's.  All handles made
+ * this way on one device share that array and keep its last contents:
+ * create and set_kinematics clear what must start at zero, and two such
+ * handles used at the same time on one device race.  ENOMEM (message naming
+ * the limit) when the lattice's regions, or the markers' at
+ * set_kinematics, exceed the array; other errors as ibmlbm_create. */
+IBMLBM_API int ibmlbm_create_noalloc(const ibmlbm_config* cfg, void* dev_state, size_t bytes,
+                                     void* hip_stream, ibmlbm_t* out);
+
 /* Place the markers of n_wings foils (n_wings = 0 removes them).  Each
  * foil's perimeter gets round(P/ds) markers at equal arc length; the
  * surface element is P/round(P/ds) x 1.  EINVAL if a marker support could

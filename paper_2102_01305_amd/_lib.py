@@ -51,6 +51,7 @@ _dp = C.POINTER(C.c_double)
 SIGNATURES = [
     ("ibmlbm_workspace_bytes", C.c_size_t, [C.POINTER(Config), C.c_int32, C.POINTER(Wing)]),
     ("ibmlbm_create", C.c_int, [C.POINTER(Config), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(Handle)]),
+    ("ibmlbm_create_noalloc", C.c_int, [C.POINTER(Config), C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(Handle)]),
     ("ibmlbm_init_fields", C.c_int, [Handle, _dp, _dp, _dp, C.c_int64]),
     ("ibmlbm_set_kinematics", C.c_int, [Handle, C.c_int32, C.POINTER(Wing)]),
     ("ibmlbm_step", C.c_int, [Handle, C.c_int32]),

@@ -875,6 +875,18 @@ int create_handle(const ibmlbm_config* cfg, void* dev_buf, size_t bytes, void* h
   if (bytes < need) return fail(nullptr, IBMLBM_ENOMEM, "workspace of %zu bytes < %zu needed", bytes, need);
   char* sb = static_cast<char*>(dev_buf);
   size_t sb_bytes = bytes;
+  if (noalloc) {
+    int dev = 0;
+    void* p = nullptr;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = scratch_address(dev, &p);
+    if (e != hipSuccess) return fail(nullptr, IBMLBM_EDEVICE, "static scratch: %s", hipGetErrorString(e));
+    if (L.end > kScratchBytes)
+      return fail(nullptr, IBMLBM_ENOMEM, "the lattice needs %zu bytes of scratch, beyond the static scratch of %zu bytes",
+                  L.end, kScratchBytes);
+    sb = static_cast<char*>(p);
+    sb_bytes = kScratchBytes;
+  }
   ibmlbm_t h = new ibmlbm_s();
   h->cfg = *cfg;
   h->stream = static_cast<hipStream_t>(hip_stream);
@@ -928,6 +940,11 @@ size_t ibmlbm_workspace_bytes(const ibmlbm_config* cfg, int32_t n_wings, const i
 int ibmlbm_create(const ibmlbm_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
                   ibmlbm_t* out) {
   return create_handle(cfg, dev_workspace, bytes, hip_stream, out, false);
+}
+
+int ibmlbm_create_noalloc(const ibmlbm_config* cfg, void* dev_state, size_t bytes, void* hip_stream,
+                          ibmlbm_t* out) {
+  return create_handle(cfg, dev_state, bytes, hip_stream, out, true);
 }
 
 int ibmlbm_init_fields(ibmlbm_t h, const double* rho, const double* u, const double* fdist, int64_t step0) {

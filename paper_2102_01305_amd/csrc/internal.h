@@ -159,4 +159,10 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
 size_t marker_span_lds(int ns);
 constexpr size_t kMaxLds = 160 * 1024;
 
+// Static scratch of ibmlbm_create_noalloc (scratch.hip): its size, and the
+// device address of a device's copy (looked up once per device).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t scratch_address(int device, void** out);
+
 }  // namespace ibmk

@@ -109,7 +109,7 @@ class Solver:
     """One D3Q19 + IBM solve on one GPU (one handle, one workspace)."""
 
     def __init__(self, bx, wings=(), storage="fp32", check_interval=0, history_steps=1024,
-                 device=None, stream=None):
+                 device=None, stream=None, noalloc=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -122,7 +122,10 @@ class Solver:
         self.wings_desc = [dict(w) for w in wings]
         self._wings = make_wings(self.wings_desc)
         nw = len(self.wings_desc)
-        nbytes = self.lib.ibmlbm_workspace_bytes(C.byref(self.cfg), nw, self._wings)
+        # noalloc: the buffer holds the two lattice states only (the lattice
+        # part of the workspace is an upper bound) and the library keeps every
+        # other region in its static device scratch (ibmlbm_create_noalloc)
+        nbytes = self.lib.ibmlbm_workspace_bytes(C.byref(self.cfg), 0 if noalloc else nw, self._wings)
         if nbytes == 0:
             raise L.IbmlbmError(L.EINVAL, self.lib.ibmlbm_last_error(None).decode())
         self.nbytes = int(nbytes)
@@ -130,7 +133,8 @@ class Solver:
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ws = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
             self.h = L.Handle()
-            L.check(self.lib.ibmlbm_create(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()), self.nbytes,
+            create = self.lib.ibmlbm_create_noalloc if noalloc else self.lib.ibmlbm_create
+            L.check(create(C.byref(self.cfg), C.c_void_p(self.ws.data_ptr()), self.nbytes,
                            C.c_void_p(self.stream.cuda_stream), C.byref(self.h)))
         if nw:
             L.check(self.lib.ibmlbm_set_kinematics(self.h, nw, self._wings), self.h)
