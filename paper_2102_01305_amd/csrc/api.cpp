@@ -56,11 +56,11 @@ struct WingGeom {
 constexpr int kPwStride = 14;      // doubles per perimeter record (markers.hip)
 
 struct MarkerLayout {
-  Region ref, G, Minv, pw, T, X, U, B, rhoB, duB, fpart, hist;
+  Region ref, G, Minv, pw, mask, T, X, U, B, rhoB, duB, fpart, hist;
   std::vector<Region> band, corr;
   size_t end = 0;
   int m_total = 0, layers = 0, perims = 0;
-  int minv_step = 0, pw_step = 0;
+  int minv_step = 0, pw_step = 0, mask_step = 0;
 };
 
 }  // namespace
@@ -526,7 +526,10 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
     maxnp = std::max(maxnp, geo[k].np);
     maxcells = std::max(maxcells, geo[k].max_cells);
   }
-  const size_t lds_factor = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 1) * maxnp) * 8;
+  int maxside = 0;
+  for (int k = 0; k < nw; ++k) maxside = std::max(maxside, geo[k].side);
+  const size_t lds_factor = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 1) * maxnp) * 8 +
+                            (size_t)maxside * ((maxside + 31) / 32) * 4;
   const size_t lds_layer = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192 +
                            (size_t)maxcells * 12;
   if (nw > 0 && std::max(lds_factor, lds_layer) > kMaxLds) {
@@ -559,6 +562,8 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
   take(M.G, nG * 8);
   take(M.Minv, (size_t)kFactorWindow * nMinv * 8);
   take(M.pw, (size_t)kFactorWindow * M.perims * kPwStride * 8);
+  for (int k = 0; k < nw; ++k) M.mask_step += geo[k].side * ((geo[k].side + 31) / 32);
+  take(M.mask, (size_t)kFactorWindow * M.mask_step * 4);
   M.minv_step = (int)nMinv;
   M.pw_step = M.perims * kPwStride;
   take(M.T, 3 * m * 8);
@@ -629,6 +634,8 @@ int record_event(ibmlbm_t h, hipStream_t st, int kind, bool start, double cells 
 // Arguments of step s whose current state is A if cur_A: the parts that
 // never change for this handle, then the step's own (state buffers, time,
 // window slot, force-history row, node boxes and the grids they imply).
+const void* dev_ma(ibmlbm_t h, int slot);
+
 void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs& ma) {
   const LatticeLayout& L = h->L;
   const ibmlbm_config& c = h->cfg;
@@ -667,6 +674,9 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ma.rhoB = at<double>(h, h->M.rhoB);
   ma.duB = at<double>(h, h->M.duB);
   ma.pw = at<double>(h, h->M.pw);
+  ma.mask = at<unsigned>(h, h->M.mask);
+  ma.mask_step = h->M.mask_step;
+  ma.win_args = static_cast<const MarkerArgs*>(dev_ma(h, 0));
   ma.T = at<double>(h, h->M.T);
   ma.fpart = at<double>(h, h->M.fpart);
   ca.fpart = ma.fpart;
@@ -704,12 +714,15 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   }
   ma.band_cells = (int)cells;
   ma.band_blocks = (int)((box_rows + 3) / 4);
-  // as many partial spread images as fit beside the layer kernel's other
-  // LDS (inverse, records, solution) in 150 KiB
+  // as many partial spread images (up to 4) as fit beside the layer
+  // kernel's other LDS (inverse, records, solution) in 80 KiB, so two layer
+  // blocks share a compute unit; where one image does not fit in that, in
+  // 150 KiB (one block per compute unit)
   const size_t fixed = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192;
   const size_t per = (size_t)maxcells * 12;
+  const size_t budget = fixed + per <= 80 * 1024 ? 80 * 1024 : 150 * 1024;
   ma.copies = 4;
-  while (ma.copies > 1 && fixed + ma.copies * per > 150 * 1024) --ma.copies;
+  while (ma.copies > 1 && fixed + ma.copies * per > budget) --ma.copies;
 }
 
 const void* dev_ca(ibmlbm_t h, int slot) {
@@ -1025,7 +1038,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
   h->win_t0 = -1;
   if (n_wings == 0) return IBMLBM_OK;
   std::vector<double> ref, G;
-  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, loff = 0;
+  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, loff = 0, maskoff = 0;
   for (int k = 0; k < n_wings; ++k) {
     const ibmlbm_wing& w = wings[k];
     h->wings[k] = w;
@@ -1037,6 +1050,8 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     d.g_off = goff;
     d.minv_off = moff2;
     d.pw_off = pwoff;
+    d.mask_off = maskoff;
+    d.mask_words = (geo[k].side + 31) / 32;
     d.c_off = 3 * moff;
     d.layer_off = loff;
     d.side = geo[k].side;
@@ -1064,6 +1079,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     goff += d.ns;
     moff2 += d.np * d.np;
     pwoff += kPwStride * d.np;
+    maskoff += d.side * d.mask_words;
     loff += d.ns;
   }
   HIP_TRY(h, hipMemcpyAsync(h->sb + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));

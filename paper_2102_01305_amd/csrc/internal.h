@@ -88,6 +88,7 @@ struct WingDev {
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
   int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
+  int mask_off, mask_words;  // offset of this foil's support mask in a window slot; 32-bit words per box row
   int c_off;                 // offset of this foil's span-solved T (ns x np x 3)
   int layer_off;             // offset of this foil's layers in the force partials
   int shape;
@@ -114,6 +115,12 @@ struct MarkerArgs {
   const double* G;
   double* Minv;              // [window slot][sum np^2] perimeter inverses
   double* pw;                // [window slot][sum np x 14] perimeter records
+  // per window slot and foil: bit (lx, ly) set where the node-box cell is a
+  // support node of some perimeter marker (the only cells whose band
+  // moments the interpolation reads); side rows of mask_words words
+  unsigned* mask;
+  int mask_step;             // words per slot
+  const MarkerArgs* win_args;  // the window's per-step arguments (device), for the node-box origins
   long long win_t0;          // first step of the precomputed window
   int slot;                  // this step's slot in the window
   int pw_step, minv_step;    // doubles per slot

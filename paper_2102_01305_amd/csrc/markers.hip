@@ -82,6 +82,29 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
   }
   __syncthreads();
   for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) Pg[e] = P[e];
+  {
+    // support mask of this step's node box: bit (lx, ly) for every node
+    // floor(X) - 1 .. floor(X) + 2 of every marker (the nodes the
+    // interpolation reads), relative to the box origin of that step
+    const WingDev& ws = a.win_args[slot].w[wi];
+    const int words = w.mask_words, rows = w.side;
+    unsigned* bits = reinterpret_cast<unsigned*>(colk + n);   // side * words words
+    for (int e = threadIdx.x; e < rows * words; e += blockDim.x) bits[e] = 0u;
+    __syncthreads();
+    for (int p = threadIdx.x; p < n; p += blockDim.x) {
+      const int bx = (int)P[p * kPw + 12] - ws.x0, by = (int)P[p * kPw + 13] - ws.y0;
+      for (int oy = 0; oy < 4; ++oy)
+        for (int ox = 0; ox < 4; ++ox) {
+          const int lx = bx + ox, ly = by + oy;
+          if (lx < 0 || ly < 0 || lx >= ws.bw || ly >= ws.bh) continue;
+          atomicOr(&bits[ly * words + (lx >> 5)], 1u << (lx & 31));
+        }
+    }
+    __syncthreads();
+    unsigned* mg = a.mask + (size_t)slot * a.mask_step + w.mask_off;
+    for (int e = threadIdx.x; e < rows * words; e += blockDim.x) mg[e] = bits[e];
+    __syncthreads();
+  }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
     const int p = e / n, q = e - p * n;
     const double* rp = P + p * kPw;
@@ -148,7 +171,9 @@ __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int
   const int lx0 = pair ? (lane & 31) : lane;
   if (ly >= w.bh) return;
   float4* out = w.band + ((long long)z * w.side + ly) * w.side;
+  const unsigned* mrow = a.mask + (size_t)a.slot * a.mask_step + w.mask_off + (size_t)ly * w.mask_words;
   for (int lx = lx0; lx < w.bw; lx += pair ? 32 : 64) {
+    if (!((mrow[lx >> 5] >> (lx & 31)) & 1u)) continue;   // not a support node: never read
     float f[kQ];
     pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
     zou_he<St, false>(a.g, a.p, w.x0 + lx, w.y0 + ly, z, f);
@@ -453,13 +478,18 @@ static hipError_t raise_lds(const void* fn, size_t bytes) {
 hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, int n, int count,
                          hipStream_t s) {
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
-  int maxnp = 0, blocks[kMaxGroup];
+  int maxnp = 0, maxmask = 0, blocks[kMaxGroup];
   for (int j = 0; j < n; ++j) {
     const MarkerArgs& a = *host[j];
-    for (int k = 0; k < a.nw; ++k) maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+    for (int k = 0; k < a.nw; ++k) {
+      maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
+      const int mw = a.w[k].side * a.w[k].mask_words;
+      maxmask = mw > maxmask ? mw : maxmask;
+    }
     blocks[j] = count * a.nw;
   }
-  const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double);
+  const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double) +
+                     (size_t)maxmask * sizeof(unsigned);
   hipError_t e = raise_lds(reinterpret_cast<const void*>(k_factor), lds);
   if (e != hipSuccess) return e;
   Group g;
