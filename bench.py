@@ -134,9 +134,19 @@ def initial_velocity(bx, ph, u_inf, seed=0):
     return u0
 
 
-def cpu_baseline(bx, wg, ph, u0, steps, rho0=None):
-    """The FP64 oracle on the host, single-threaded, over `steps` steps of
-    the same workload (setup excluded)."""
+def host_cores():
+    """Host cores this process may run on (the machine's CPU share)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_rate(bx, wg, ph, u0, steps, rho0=None, lattice="numpy", threads=1):
+    """MLUPS of the FP64 oracle over `steps` whole steps (setup excluded):
+    lattice.py (NumPy, single-threaded by construction: element-wise array
+    operations) or its C lattice with OpenMP over z-planes on `threads`
+    threads; the marker part is NumPy/SciPy either way."""
     from threadpoolctl import threadpool_limits
 
     from oracle import params
@@ -146,19 +156,44 @@ def cpu_baseline(bx, wg, ph, u0, steps, rho0=None):
         ob, ow = bx, wg
     else:
         ob, ow = params.complete_case(bx, wg, ph)
-    with threadpool_limits(limits=1):
-        s = Sim(ob, ow, rho0=rho0, u0=u0)
+    if lattice == "c":
+        from oracle import clattice
+        clattice.set_threads(threads)
+    with threadpool_limits(limits=threads):
+        s = Sim(ob, ow, rho0=rho0, u0=u0, lattice=lattice)
         t0 = time.perf_counter()
         s.run(steps)
         dt = time.perf_counter() - t0
     n = bx["nx"] * bx["ny"] * bx["nz"]
-    return dict(value=n * steps / dt / 1e6, unit="MLUPS", cores=1, kind="oracle",
-                sample=f"{steps} full step(s) of the same workload "
-                       f"({bx['nx']}x{bx['ny']}x{bx['nz']}, all markers), FP64 NumPy, "
-                       f"{dt:.1f} s")
+    return n * steps / dt / 1e6, dt
 
 
-def serve_bench(budget_bytes, steps, log=None):
+def cpu_baseline(name, bx, wg, ph, u0, steps, rho0=None):
+    """The FP64 oracle on the host: the plain NumPy oracle on one core over
+    `steps` steps of the benchmark workload; beside it the oracle with its
+    C lattice on every host core over a longer window of the same workload,
+    and the NumPy oracle over the whole 200-step plate workload."""
+    cores = host_cores()
+    v1, t1 = _oracle_rate(bx, wg, ph, u0, steps, rho0)
+    out = dict(value=round(v1, 3), unit="MLUPS", cores=1, host_cores=cores, kind="oracle",
+               sample=f"{steps} whole step(s) of {name} ({bx['nx']}x{bx['ny']}x{bx['nz']}, every marker), "
+                      f"FP64 NumPy oracle on one core, {t1:.1f} s")
+    if ph["kind"] != "taylor_green":
+        va, ta = _oracle_rate(bx, wg, ph, u0, 4 * steps, rho0, lattice="c", threads=cores)
+        out["all_cores"] = dict(value=round(va, 3), unit="MLUPS", cores=cores,
+                                sample=f"{4 * steps} whole steps of {name}, FP64 oracle with its C lattice "
+                                       f"(OpenMP over z-planes) on {cores} threads, {ta:.1f} s")
+    pb, pw, pp = WL.plate_case()
+    pu = WL.velocity_noise((pb["nz"], pb["ny"], pb["nx"]), 0)
+    pu[0] += pp["u_inf"]
+    vp, tp = _oracle_rate(pb, pw, pp, pu, 200)
+    out["plate_200_steps"] = dict(value=round(vp, 3), unit="MLUPS", cores=1,
+                                  sample=f"the 64x32x32 plate workload in full (200 steps), FP64 NumPy oracle "
+                                         f"on one core, {tp:.1f} s")
+    return out
+
+
+def serve_bench(budget_bytes, steps, storage="fp32"):
     """The seeded 64-request sweep (Re x J x f x domain) served twice: all
     arriving at once (capacity), then with Poisson arrivals at 0.8 of that
     capacity.  Returns the summaries."""
@@ -180,7 +215,7 @@ def serve_bench(budget_bytes, steps, log=None):
                 return u
 
             out.append(SweepRequest(rid=q["id"], box=gb, wings=gw, steps=q["steps"],
-                                    arrival=q["arrival"], u0=u0))
+                                    arrival=q["arrival"], u0=u0, storage=storage))
         return out
 
     res = {}
@@ -272,7 +307,7 @@ def main():
     ap.add_argument("--workload", default="cf")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--timing-every", type=int, default=8,
                     help="bracket the kernels of one step in this many with HIP events")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -338,17 +373,20 @@ def main():
                         "marker_ms_per_step": round(vf["marker_ms"], 5)})
         out["variants"] = var
     if not args.no_serve:
-        print("[bench] served sweep: 64 requests", file=sys.stderr, flush=True)
-        sv = serve_bench(int(args.serve_budget_gib * 2**30), args.serve_steps)
-        out["serving"] = {
-            "requests": 64, "steps_per_request": args.serve_steps,
-            "hbm_budget_gib": args.serve_budget_gib, "storage": "fp32",
-            "burst": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["burst"].items()},
-            "poisson": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["poisson"].items()},
-        }
+        serving = []
+        for sto in ("fp32", "fp16"):
+            print(f"[bench] served sweep: 64 requests, {sto}", file=sys.stderr, flush=True)
+            sv = serve_bench(int(args.serve_budget_gib * 2**30), args.serve_steps, sto)
+            serving.append({
+                "requests": 64, "steps_per_request": args.serve_steps,
+                "hbm_budget_gib": args.serve_budget_gib, "storage": sto,
+                "burst": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["burst"].items()},
+                "poisson": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in sv["poisson"].items()},
+            })
+        out["serving"] = serving
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(bx, wg, ph, u0, args.cpu_steps, rho0)
+        out["cpu_baseline"] = cpu_baseline(name, bx, wg, ph, u0, args.cpu_steps, rho0)
     print(json.dumps(out), flush=True)
 
 

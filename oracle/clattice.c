@@ -15,6 +15,8 @@
  */
 #include <stddef.h>
 
+#include <omp.h>
+
 enum { Q = 19 };
 enum { PERIODIC = 0, WALL = 1, VELOCITY = 2, PRESSURE = 3, ZH_VELOCITY = 4, ZH_PRESSURE = 5 };
 
@@ -216,4 +218,9 @@ void ora_equilibrium(const double* rho, const double* u, double* out, int nx, in
     for (size_t cell = (size_t)z * ny * nx; cell < (size_t)(z + 1) * ny * nx; ++cell)
       for (int i = 0; i < Q; ++i)
         out[(size_t)i * N + cell] = feq(i, rho[cell], u[cell], u[N + cell], u[2 * N + cell]);
+}
+
+/* Threads of the parallel loops above (the OpenMP default is the host's). */
+void ora_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
 }

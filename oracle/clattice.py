@@ -48,10 +48,16 @@ def _load():
         lib.ora_moments.argtypes = [dp, dp, dp, i, i, i]
         lib.ora_collide.argtypes = [dp, dp, dp, dp, C.c_double, dp, i, i, i]
         lib.ora_equilibrium.argtypes = [dp, dp, dp, i, i, i]
-        for fn in (lib.ora_stream, lib.ora_moments, lib.ora_collide, lib.ora_equilibrium):
+        lib.ora_set_threads.argtypes = [i]
+        for fn in (lib.ora_stream, lib.ora_moments, lib.ora_collide, lib.ora_equilibrium, lib.ora_set_threads):
             fn.restype = None
         _lib = lib
     return _lib
+
+
+def set_threads(n):
+    """Threads of the C lattice's parallel loops."""
+    _load().ora_set_threads(int(n))
 
 
 def _p(a):
