@@ -714,13 +714,19 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   }
   ma.band_cells = (int)cells;
   ma.band_blocks = (int)((box_rows + 3) / 4);
-  // as many partial spread images (up to 4) as fit beside the layer
-  // kernel's other LDS (inverse, records, solution) in 80 KiB, so two layer
-  // blocks share a compute unit; where one image does not fit in that, in
-  // 150 KiB (one block per compute unit)
-  const size_t fixed = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192;
+  // Layer kernel LDS: the perimeter inverse (staged where two blocks with
+  // one spread image still fit a compute unit, else read from L2), the
+  // records and the layer's solution, an 8 KiB reduction array, and as many
+  // partial spread images (up to 4) as fit in the budget: two blocks per
+  // compute unit with the inverse staged, three with it read from L2, else
+  // as many as fit.
+  const size_t inv = (size_t)maxnp * maxnp * 8;
+  const size_t rest = (size_t)(kPwStride + 6) * maxnp * 8 + 8192;
   const size_t per = (size_t)maxcells * 12;
-  const size_t budget = fixed + per <= 80 * 1024 ? 80 * 1024 : 150 * 1024;
+  ma.minv_global = inv + rest + per > 80 * 1024;
+  const size_t fixed = ma.minv_global ? rest : inv + rest;
+  size_t budget = 80 * 1024;
+  if (ma.minv_global) budget = fixed + per <= 53 * 1024 ? 53 * 1024 : (fixed + per <= 80 * 1024 ? 80 * 1024 : 150 * 1024);
   ma.copies = 4;
   while (ma.copies > 1 && fixed + ma.copies * per > budget) --ma.copies;
 }
