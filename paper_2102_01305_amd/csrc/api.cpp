@@ -56,11 +56,11 @@ struct WingGeom {
 constexpr int kPwStride = 14;      // doubles per perimeter record (markers.hip)
 
 struct MarkerLayout {
-  Region ref, G, Minv, pw, mask, T, X, U, B, rhoB, duB, fpart, hist;
+  Region ref, G, Minv, pw, sup, T, X, U, B, rhoB, duB, fpart, hist;
   std::vector<Region> band, corr;
   size_t end = 0;
   int m_total = 0, layers = 0, perims = 0;
-  int minv_step = 0, pw_step = 0, mask_step = 0;
+  int minv_step = 0, pw_step = 0, sup_step = 0;
 };
 
 }  // namespace
@@ -353,6 +353,30 @@ void node_box(const ibmlbm_wing& w, const WingGeom& g, double t, const ibmlbm_co
   d.bh = std::min(by1 - by0 + 1, g.side);
 }
 
+// Bound on the number of support nodes of a foil at time t in its node box
+// d: the marker kernels list the nodes floor(X) - 1 .. floor(X) + 2 of every
+// marker from positions they compute themselves; taking both floors of
+// X -/+ 1e-9 here gives a set that contains theirs.
+int support_bound(const ibmlbm_wing& w, const WingGeom& g, double t, const WingDev& d) {
+  std::vector<double> xy;
+  perimeter_xy(w, g, t, xy);
+  std::vector<unsigned char> hit((size_t)d.bw * d.bh, 0);
+  int cnt = 0;
+  for (int p = 0; p < g.np; ++p) {
+    const int xa = std::max(0, (int)std::floor(xy[2 * p] - 1e-9) - 1 - d.x0);
+    const int xb = std::min(d.bw - 1, (int)std::floor(xy[2 * p] + 1e-9) + 2 - d.x0);
+    const int ya = std::max(0, (int)std::floor(xy[2 * p + 1] - 1e-9) - 1 - d.y0);
+    const int yb = std::min(d.bh - 1, (int)std::floor(xy[2 * p + 1] + 1e-9) + 2 - d.y0);
+    for (int ly = ya; ly <= yb; ++ly)
+      for (int lx = xa; lx <= xb; ++lx) {
+        unsigned char& m = hit[(size_t)ly * d.bw + lx];
+        cnt += m == 0;
+        m = 1;
+      }
+  }
+  return cnt;
+}
+
 // Smallest Cholesky pivot of the perimeter block relative to its largest
 // diagonal entry; <= 0 means not positive definite.
 double perimeter_conditioning(const std::vector<double>& xy, int n, const ibmlbm_config& c) {
@@ -529,7 +553,7 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
   int maxside = 0;
   for (int k = 0; k < nw; ++k) maxside = std::max(maxside, geo[k].side);
   const size_t lds_factor = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 1) * maxnp) * 8 +
-                            (size_t)maxside * ((maxside + 31) / 32) * 4;
+                            (size_t)maxside * ((maxside + 31) / 32 + 1) * 4;
   const size_t lds_layer = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192 +
                            (size_t)maxcells * 12;
   if (nw > 0 && std::max(lds_factor, lds_layer) > kMaxLds) {
@@ -562,8 +586,8 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
   take(M.G, nG * 8);
   take(M.Minv, (size_t)kFactorWindow * nMinv * 8);
   take(M.pw, (size_t)kFactorWindow * M.perims * kPwStride * 8);
-  for (int k = 0; k < nw; ++k) M.mask_step += geo[k].side * ((geo[k].side + 31) / 32);
-  take(M.mask, (size_t)kFactorWindow * M.mask_step * 4);
+  for (int k = 0; k < nw; ++k) M.sup_step += 1 + 16 * geo[k].np;
+  take(M.sup, (size_t)kFactorWindow * M.sup_step * 4);
   M.minv_step = (int)nMinv;
   M.pw_step = M.perims * kPwStride;
   take(M.T, 3 * m * 8);
@@ -674,8 +698,8 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   ma.rhoB = at<double>(h, h->M.rhoB);
   ma.duB = at<double>(h, h->M.duB);
   ma.pw = at<double>(h, h->M.pw);
-  ma.mask = at<unsigned>(h, h->M.mask);
-  ma.mask_step = h->M.mask_step;
+  ma.sup = at<unsigned>(h, h->M.sup);
+  ma.sup_step = h->M.sup_step;
   ma.win_args = static_cast<const MarkerArgs*>(dev_ma(h, 0));
   ma.T = at<double>(h, h->M.T);
   ma.fpart = at<double>(h, h->M.fpart);
@@ -698,7 +722,7 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   }
   ma.src = ca.src;
   ca.hist_row = s % c.history_steps;
-  long long cells = 0, box_rows = 0;
+  long long cells = 0, band_waves = 0;
   int maxnp = 0, maxcells = 0;
   for (int w = 0; w < h->nw; ++w) {
     node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
@@ -708,12 +732,13 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     b.band = ma.w[w].band;
     b.corr = ma.w[w].corr;
     cells += (long long)b.w * b.h * c.nz;
-    box_rows += (long long)(ma.w[w].bw <= 32 ? (ma.w[w].bh + 1) / 2 : ma.w[w].bh) * c.nz;   // band waves
+    ma.w[w].sup_chunks = (support_bound(h->wings[w], h->geom[w], (double)s, ma.w[w]) + 63) / 64;
+    band_waves += (long long)ma.w[w].sup_chunks * c.nz;
     maxnp = std::max(maxnp, ma.w[w].np);
     maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
   }
   ma.band_cells = (int)cells;
-  ma.band_blocks = (int)((box_rows + 3) / 4);
+  ma.band_blocks = (int)((band_waves + 3) / 4);
   // Layer kernel LDS: the perimeter inverse (staged where two blocks with
   // one spread image still fit a compute unit, else read from L2), the
   // records and the layer's solution, an 8 KiB reduction array, and as many
@@ -1044,7 +1069,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
   h->win_t0 = -1;
   if (n_wings == 0) return IBMLBM_OK;
   std::vector<double> ref, G;
-  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, loff = 0, maskoff = 0;
+  int moff = 0, roff = 0, goff = 0, moff2 = 0, pwoff = 0, loff = 0, supoff = 0;
   for (int k = 0; k < n_wings; ++k) {
     const ibmlbm_wing& w = wings[k];
     h->wings[k] = w;
@@ -1056,7 +1081,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     d.g_off = goff;
     d.minv_off = moff2;
     d.pw_off = pwoff;
-    d.mask_off = maskoff;
+    d.sup_off = supoff;
     d.mask_words = (geo[k].side + 31) / 32;
     d.c_off = 3 * moff;
     d.layer_off = loff;
@@ -1085,7 +1110,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     goff += d.ns;
     moff2 += d.np * d.np;
     pwoff += kPwStride * d.np;
-    maskoff += d.side * d.mask_words;
+    supoff += 1 + 16 * d.np;
     loff += d.ns;
   }
   HIP_TRY(h, hipMemcpyAsync(h->sb + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));

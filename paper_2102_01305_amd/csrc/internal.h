@@ -88,7 +88,9 @@ struct WingDev {
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
   int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
-  int mask_off, mask_words;  // offset of this foil's support mask in a window slot; 32-bit words per box row
+  int sup_off;               // offset of this foil's support list in a window slot (1 + np*16 words)
+  int mask_words;            // 32-bit words per node-box row of the support bitmap
+  int sup_chunks;            // this step's band waves per layer: 64-cell chunks of a bound on its support count
   int c_off;                 // offset of this foil's span-solved T (ns x np x 3)
   int layer_off;             // offset of this foil's layers in the force partials
   int shape;
@@ -105,7 +107,7 @@ struct MarkerArgs {
   int nw;
   int m_total;
   int band_cells;            // sum over foils of bw*bh*nz
-  int band_blocks;           // blocks of 4 band waves (a row each, or two rows of a box <= 32 wide)
+  int band_blocks;           // blocks of 4 band waves (64 support cells of one foil's layer each)
   WingDev w[kMaxWings];
   double wz[4];              // span weights of a node at offsets -1.5, -0.5, 0.5, 1.5
   double t;
@@ -115,11 +117,11 @@ struct MarkerArgs {
   const double* G;
   double* Minv;              // [window slot][sum np^2] perimeter inverses
   double* pw;                // [window slot][sum np x 14] perimeter records
-  // per window slot and foil: bit (lx, ly) set where the node-box cell is a
-  // support node of some perimeter marker (the only cells whose band
-  // moments the interpolation reads); side rows of mask_words words
-  unsigned* mask;
-  int mask_step;             // words per slot
+  // per window slot and foil: the support nodes of its perimeter markers
+  // (the only node-box cells whose band moments the interpolation reads),
+  // as a count and then ly << 16 | lx per cell, row-major
+  unsigned* sup;
+  int sup_step;              // words per slot
   const MarkerArgs* win_args;  // the window's per-step arguments (device), for the node-box origins
   long long win_t0;          // first step of the precomputed window
   int slot;                  // this step's slot in the window

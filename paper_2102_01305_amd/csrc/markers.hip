@@ -83,12 +83,14 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
   __syncthreads();
   for (int e = threadIdx.x; e < n * kPw; e += blockDim.x) Pg[e] = P[e];
   {
-    // support mask of this step's node box: bit (lx, ly) for every node
+    // support nodes of this step's node box: bit (lx, ly) for every node
     // floor(X) - 1 .. floor(X) + 2 of every marker (the nodes the
-    // interpolation reads), relative to the box origin of that step
+    // interpolation reads), relative to the box origin of that step; then
+    // the set bits as a row-major list of ly << 16 | lx after their count
     const WingDev& ws = a.win_args[slot].w[wi];
     const int words = w.mask_words, rows = w.side;
     unsigned* bits = reinterpret_cast<unsigned*>(colk + n);   // side * words words
+    int* rc = reinterpret_cast<int*>(bits + rows * words);    // side row counts
     for (int e = threadIdx.x; e < rows * words; e += blockDim.x) bits[e] = 0u;
     __syncthreads();
     for (int p = threadIdx.x; p < n; p += blockDim.x) {
@@ -101,8 +103,27 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
         }
     }
     __syncthreads();
-    unsigned* mg = a.mask + (size_t)slot * a.mask_step + w.mask_off;
-    for (int e = threadIdx.x; e < rows * words; e += blockDim.x) mg[e] = bits[e];
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+      int c = 0;
+      for (int q = 0; q < words; ++q) c += __popc(bits[r * words + q]);
+      rc[r] = c;
+    }
+    __syncthreads();
+    unsigned* out = a.sup + (size_t)slot * a.sup_step + w.sup_off;
+    for (int r = threadIdx.x; r < rows; r += blockDim.x) {
+      int o = 0;
+      for (int q = 0; q < r; ++q) o += rc[q];
+      unsigned* e = out + 1 + o;
+      for (int q = 0; q < words; ++q) {
+        unsigned b = bits[r * words + q];
+        while (b) {
+          const int bit = __ffs(b) - 1;
+          b &= b - 1;
+          *e++ = ((unsigned)r << 16) | (unsigned)(q * 32 + bit);
+        }
+      }
+      if (r == rows - 1) out[0] = (unsigned)(o + rc[r]);
+    }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
@@ -147,9 +168,10 @@ __global__ void __launch_bounds__(256) k_factor(Group gr) {
 }
 
 // rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
-// pre-collision state at every node of every foil's box, on every layer.
-// One wave per box row (y, z), lanes along x; a box at most 32 wide gives a
-// wave two neighbouring rows, one per half.
+// pre-collision state at the support nodes of every foil's markers, on every
+// layer.  One wave per 64 entries of a foil's support list on one layer;
+// waves past the list's length (the host sizes the grid from a bound) end at
+// once.
 template <class St>
 __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int lb) {
   using T = typename St::T;
@@ -157,32 +179,27 @@ __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int
   const int lane = threadIdx.x & 63;
   int wi = 0;
   while (wi < a.nw) {
-    const int units = (a.w[wi].bw <= 32 ? (a.w[wi].bh + 1) / 2 : a.w[wi].bh) * a.g.nz;
+    const int units = a.w[wi].sup_chunks * a.g.nz;
     if (R < units) break;
     R -= units;
     ++wi;
   }
   if (wi >= a.nw) return;
   const WingDev& w = a.w[wi];
-  const bool pair = w.bw <= 32;
-  const int per = pair ? (w.bh + 1) / 2 : w.bh;
-  const int z = R / per, q = R - z * per;
-  const int ly = pair ? 2 * q + (lane >> 5) : q;
-  const int lx0 = pair ? (lane & 31) : lane;
-  if (ly >= w.bh) return;
-  float4* out = w.band + ((long long)z * w.side + ly) * w.side;
-  const unsigned* mrow = a.mask + (size_t)a.slot * a.mask_step + w.mask_off + (size_t)ly * w.mask_words;
-  for (int lx = lx0; lx < w.bw; lx += pair ? 32 : 64) {
-    if (!((mrow[lx >> 5] >> (lx & 31)) & 1u)) continue;   // not a support node: never read
-    float f[kQ];
-    pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
-    zou_he<St, false>(a.g, a.p, w.x0 + lx, w.y0 + ly, z, f);
-    float drho, jx, jy, jz;
-    moments19(f, drho, jx, jy, jz);
-    const float rho = 1.0f + drho;
-    out[lx] = make_float4(rho, (jx + 0.5f * a.p.fb[0]) / rho, (jy + 0.5f * a.p.fb[1]) / rho,
-                          (jz + 0.5f * a.p.fb[2]) / rho);
-  }
+  const int z = R / w.sup_chunks, chunk = R - z * w.sup_chunks;
+  const auto* list = gmem(a.sup + (size_t)a.slot * a.sup_step + w.sup_off);
+  const int e = chunk * 64 + lane;
+  if (e >= (int)list[0]) return;
+  const unsigned cell = list[1 + e];
+  const int lx = (int)(cell & 0xffffu), ly = (int)(cell >> 16);
+  float f[kQ];
+  pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
+  zou_he<St, false>(a.g, a.p, w.x0 + lx, w.y0 + ly, z, f);
+  float drho, jx, jy, jz;
+  moments19(f, drho, jx, jy, jz);
+  const float rho = 1.0f + drho;
+  w.band[((long long)z * w.side + ly) * w.side + lx] =
+      make_float4(rho, (jx + 0.5f * a.p.fb[0]) / rho, (jy + 0.5f * a.p.fb[1]) / rho, (jz + 0.5f * a.p.fb[2]) / rho);
 }
 
 template <class St>
@@ -203,9 +220,10 @@ __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, in
 
 // Block (foil, perimeter marker p): the marker's delta interpolation on
 // every span layer and the span part of the minimum-norm solve.
-//  * The band records of the marker's 4 x 4 xy support nodes on every layer
-//    are read once into LDS.  D = D_xy wz factors, so per layer z the xy sum
-//    R(z) = sum_nodes D_xy band(node, z) is made once (FP64), and rho_B and
+//  * D = D_xy wz factors, so per layer z the xy sum
+//    R(z) = sum_nodes D_xy band(node, z) over the marker's 4 x 4 xy support
+//    nodes is made once (FP64; a thread loads the 16 band records of its
+//    layer together), and rho_B and
 //    I u* at the marker on layer s are sum_k wz_k R(s - 1 + k), k = 0..3
 //    (Eq. 17); B = U_B - I u* (Eq. 19).
 //  * T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
@@ -220,14 +238,13 @@ __host__ __device__ inline int parts_at(int ns, int threads) {
 }
 
 // LDS of a block: G (2 ns), B (3 ns), partial sums (parts x 3 ns), the xy
-// sums R (4 ns), the marker's record, then the band records (16 ns float4,
-// 16-byte aligned).
+// sums R (4 ns) and the marker's record.
 __host__ __device__ inline size_t interp_span_doubles(int ns, int parts) {
   const size_t d = (size_t)(9 + 3 * parts) * ns + kPw;
   return (d + 1) / 2 * 2;
 }
 __host__ __device__ inline size_t lds_at(int ns, int threads) {
-  return interp_span_doubles(ns, parts_at(ns, threads)) * sizeof(double) + 16 * (size_t)ns * 16;
+  return interp_span_doubles(ns, parts_at(ns, threads)) * sizeof(double);
 }
 
 // Threads of an interp_span block for a span of ns layers: 512 (more parts
@@ -257,7 +274,6 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
   double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
   double* R = Pa + (size_t)parts * 3 * ns;                              // 4 * ns
   double* r = R + 4 * ns;                                               // kPw
-  float4* rec = reinterpret_cast<float4*>(lds + interp_span_doubles(ns, parts));  // [node][layer]
   const auto* Gg = gmem(a.G + w.g_off);
   for (int i = threadIdx.x; i < ns; i += bd) {
     const double g = Gg[i];
@@ -266,37 +282,36 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
   }
   copy_to_lds(r, a.pw + (size_t)a.slot * a.pw_step + w.pw_off + (size_t)p * kPw, kPw);
   __syncthreads();
+  const double thd = a.pose[wi][1], vx = a.pose[wi][4], vy = a.pose[wi][5];
+  const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
   {
+    // the 16 band records of layer z, loaded together straight from L2
     const int bx = (int)r[12] - w.x0, by = (int)r[13] - w.y0;
     typedef float v4f __attribute__((ext_vector_type(4)));   // one 16-byte load per record
     const auto* band = gmem(reinterpret_cast<const v4f*>(w.band));
-    for (int e = threadIdx.x; e < 16 * ns; e += bd) {
-      const int node = e / ns, z = e - node * ns;
-      const v4f v = band[((long long)z * w.side + by + (node >> 2)) * w.side + bx + (node & 3)];
-      rec[e] = make_float4(v.x, v.y, v.z, v.w);
-    }
-  }
-  __syncthreads();
-  const double thd = a.pose[wi][1], vx = a.pose[wi][4], vy = a.pose[wi][5];
-  const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
-  for (int z = threadIdx.x; z < ns; z += bd) {
-    double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
+    for (int z = threadIdx.x; z < ns; z += bd) {
+      const auto* row0 = band + ((long long)z * w.side + by) * w.side + bx;
+      v4f v[16];
 #pragma unroll
-    for (int oy = 0; oy < 4; ++oy) {
+      for (int node = 0; node < 16; ++node) v[node] = row0[(node >> 2) * w.side + (node & 3)];
+      double R0 = 0.0, R1 = 0.0, R2 = 0.0, R3 = 0.0;
 #pragma unroll
-      for (int ox = 0; ox < 4; ++ox) {
-        const float4 v = rec[(size_t)(oy * 4 + ox) * ns + z];
-        const double D = r[4 + ox] * r[8 + oy];
-        R0 += D * (double)v.x;
-        R1 += D * (double)v.y;
-        R2 += D * (double)v.z;
-        R3 += D * (double)v.w;
+      for (int oy = 0; oy < 4; ++oy) {
+#pragma unroll
+        for (int ox = 0; ox < 4; ++ox) {
+          const v4f q = v[oy * 4 + ox];
+          const double D = r[4 + ox] * r[8 + oy];
+          R0 += D * (double)q.x;
+          R1 += D * (double)q.y;
+          R2 += D * (double)q.z;
+          R3 += D * (double)q.w;
+        }
       }
+      R[4 * z] = R0;
+      R[4 * z + 1] = R1;
+      R[4 * z + 2] = R2;
+      R[4 * z + 3] = R3;
     }
-    R[4 * z] = R0;
-    R[4 * z + 1] = R1;
-    R[4 * z + 2] = R2;
-    R[4 * z + 3] = R3;
   }
   __syncthreads();
   for (int s = threadIdx.x; s < ns; s += bd) {
@@ -327,12 +342,12 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
     }
   }
   __syncthreads();
-  // parts in turns of bd / groups (>= 1: ns <= 1024 is checked on the host)
-  const int t = (int)threadIdx.x % groups;
-  for (int part = (int)threadIdx.x / groups; part < parts && (int)threadIdx.x < (bd / groups) * groups;
-       part += bd / groups) {
+  // items (part, four outputs s0 = 4 t) in turns of the block
+  for (int item = threadIdx.x; item < parts * groups; item += bd) {
+    const int part = item / groups, t = item - part * groups;
     const int lo = part * ns / parts, hi = (part + 1) * ns / parts;
-    for (int s0 = 4 * t; s0 < ns; s0 += 4 * groups) {
+    {
+      const int s0 = 4 * t;
       double acc[4][3];
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
@@ -500,7 +515,7 @@ hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, 
     const MarkerArgs& a = *host[j];
     for (int k = 0; k < a.nw; ++k) {
       maxnp = a.w[k].np > maxnp ? a.w[k].np : maxnp;
-      const int mw = a.w[k].side * a.w[k].mask_words;
+      const int mw = a.w[k].side * (a.w[k].mask_words + 1);   // bitmap and row counts
       maxmask = mw > maxmask ? mw : maxmask;
     }
     blocks[j] = count * a.nw;

@@ -196,19 +196,19 @@ def test_one_layer_span_is_accepted_only_periodic():
 
 
 def test_span_longer_than_the_marker_block_is_rejected():
-    """One block holds every span layer of a marker (its band records, B and
-    the span solve) in local memory, so spans have a limit; the lattice alone
-    has none, and the limit is named in the error."""
+    """One block holds every span layer of a marker (its layer sums, B, the
+    partial sums of the span solve) in local memory, so spans have a limit;
+    the lattice alone has none, and the limit is named in the error."""
     L, lib = _lib()
     bx, wg = _plate()
     from paper_2102_01305_amd.solver import make_wings
-    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=384))), 1, make_wings(wg)) > 0
-    long_span = dict(bx, nz=1024)
+    assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=1024))), 1, make_wings(wg)) > 0
+    long_span = dict(bx, nz=4096)
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(long_span)), 0, None) > 0
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(long_span)), 1, make_wings(wg)) == 0
     msg = lib.ibmlbm_last_error(None).decode()
-    assert "span of 1024 layers" in msg
+    assert "span of 4096 layers" in msg
     top = int(msg.rsplit("at most ", 1)[1].rstrip(")"))
-    assert 384 <= top < 1024
+    assert 1024 <= top < 4096
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top))), 1, make_wings(wg)) > 0
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top + 1))), 1, make_wings(wg)) == 0
