@@ -295,8 +295,8 @@ def timed_solve(wname, storage, steps, warmup, timing_every):
 
 # The storage formats and the largest workload, measured beside the headline
 # line of the default run: (workload, storage, steps, warmup).
-VARIANTS = (("cf", "fp16", 300, 20), ("cf", "bf16", 300, 20), ("large", "fp32", 50, 5),
-            ("large", "fp16", 50, 5), ("tgv", "fp16", 200, 20))
+VARIANTS = (("cf", "fp16", 320, 64), ("cf", "bf16", 320, 64), ("large", "fp32", 64, 64),
+            ("large", "fp16", 64, 64), ("tgv", "fp16", 200, 20))
 
 
 def main():

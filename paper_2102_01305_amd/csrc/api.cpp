@@ -542,9 +542,10 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
     }
   }
   // local memory of the marker kernels: the perimeter factor block holds the
-  // n_p x n_p matrix, the records and a column; the layer block holds the
-  // inverse, the records, the layer's solution, at least one partial spread
-  // image of the largest node box and an 8 KB reduction array (markers.hip)
+  // records, the pivot column and row (the matrix itself is in registers)
+  // and the support bitmap; the layer block holds the inverse, the records,
+  // the layer's solution, at least one partial spread image of the largest
+  // node box and an 8 KB reduction array (markers.hip)
   int maxnp = 0, maxcells = 0;
   for (int k = 0; k < nw; ++k) {
     maxnp = std::max(maxnp, geo[k].np);
@@ -552,8 +553,7 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
   }
   int maxside = 0;
   for (int k = 0; k < nw; ++k) maxside = std::max(maxside, geo[k].side);
-  const size_t lds_factor = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 1) * maxnp) * 8 +
-                            (size_t)maxside * ((maxside + 31) / 32 + 1) * 4;
+  const size_t lds_factor = (size_t)(kPwStride + 4) * maxnp * 8 + (size_t)maxside * ((maxside + 31) / 32 + 1) * 4;
   const size_t lds_layer = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192 +
                            (size_t)maxcells * 12;
   if (nw > 0 && std::max(lds_factor, lds_layer) > kMaxLds) {

@@ -34,30 +34,36 @@ __device__ __forceinline__ double delta_k(double r) {
 
 // a(p, q) = sum_j delta(j - X_p) delta(j - X_q) from the two 4-node weight
 // sets (1D factor of Eq. 18).
+// Branch-free: every weight is loaded whatever the offset, so the loads of
+// many entries can be in flight together; a term outside the overlap adds
+// an exact zero.
 __device__ __forceinline__ double a1(const double* wp, int bp, const double* wq, int bq) {
   const int d = bq - bp;
   double s = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int kk = k - d;
-    if (kk >= 0 && kk < 4) s += wp[k] * wq[kk];
+    const bool in = kk >= 0 && kk < 4;
+    const double t = wp[k] * wq[in ? kk : 0];
+    s += in ? t : 0.0;
   }
   return s;
 }
 
 // Perimeter positions and weights of foil `wi` at time t, the block
 // M_xy[p][q] = a(X_p, X_q) a(Y_p, Y_q) and its inverse by in-place
-// Gauss-Jordan (symmetric positive definite: no pivoting), FP64 in LDS.
+// Gauss-Jordan (symmetric positive definite: no pivoting), FP64 in
+// registers.
 // These depend on the prescribed kinematics only, so they are computed for a
 // window of future steps at once, one block per (step, foil).
+template <int NT>
 __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
   const int slot = lb / a.nw, wi = lb - slot * a.nw;
   const WingDev& w = a.w[wi];
   const int n = w.np;
-  double* M = lds;              // n * n
-  double* P = lds + n * n;      // n * kPw
-  double* colk = P + n * kPw;   // n
+  double* P = lds;              // n * kPw
+  double* CR = P + n * kPw;     // 2 sets of (column k, row k) of the elimination, 4 n
   double th, thd, hx, hy, vx, vy;
   wing_pose(w, (double)(a.win_t0 + slot), th, thd, hx, hy, vx, vy);
   const double c = cos(th), sn = sin(th);
@@ -89,7 +95,7 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
     // the set bits as a row-major list of ly << 16 | lx after their count
     const WingDev& ws = a.win_args[slot].w[wi];
     const int words = w.mask_words, rows = w.side;
-    unsigned* bits = reinterpret_cast<unsigned*>(colk + n);   // side * words words
+    unsigned* bits = reinterpret_cast<unsigned*>(CR + 4 * n);   // side * words words
     int* rc = reinterpret_cast<int*>(bits + rows * words);    // side row counts
     for (int e = threadIdx.x; e < rows * words; e += blockDim.x) bits[e] = 0u;
     __syncthreads();
@@ -126,45 +132,94 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
     }
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int p = e / n, q = e - p * n;
-    const double* rp = P + p * kPw;
-    const double* rq = P + q * kPw;
-    M[e] = a1(rp + 4, (int)rp[12], rq + 4, (int)rq[12]) * a1(rp + 8, (int)rp[13], rq + 8, (int)rq[13]);
-  }
-  __syncthreads();
+  // The block M[p][q] = a(X_p, X_q) a(Y_p, Y_q) and its inverse by
+  // Gauss-Jordan without pivoting (symmetric positive definite), FP64.
+  // Thread (ty, tx) of a 16 x 16 grid holds the elements (ty + 16 u,
+  // tx + 16 v), u, v < NT (16 NT >= n), in registers; for pivot k the owners
+  // of column k and of row k publish them in LDS (two sets, by the parity of
+  // k, so one barrier per pivot).  Entries outside the n x n block are
+  // carried along without branches and never read into the block.
+  const int tx = (int)threadIdx.x & 15, ty = (int)threadIdx.x >> 4;
+  double Mr[NT][NT];
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int v = 0; v < NT; ++v) {
+      const int p = ty + 16 * u, q = tx + 16 * v;
+      double val = 0.0;
+      if (p < n && q < n) {
+        const double* rp = P + p * kPw;
+        const double* rq = P + q * kPw;
+        val = a1(rp + 4, (int)rp[12], rq + 4, (int)rq[12]) * a1(rp + 8, (int)rp[13], rq + 8, (int)rq[13]);
+      }
+      Mr[u][v] = val;
+    }
   __shared__ int singular;
   if (threadIdx.x == 0) singular = 0;
-  __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const double piv = M[k * n + k];
+    double* col = CR + (k & 1) * 2 * n;
+    double* row = col + n;
+    const int kb = k >> 4, kt = k & 15;
+    if (tx == kt) {
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        double m = 0.0;
+#pragma unroll
+        for (int v = 0; v < NT; ++v) m = v == kb ? Mr[u][v] : m;
+        if (ty + 16 * u < n) col[ty + 16 * u] = m;
+      }
+    }
+    if (ty == kt) {
+#pragma unroll
+      for (int v = 0; v < NT; ++v) {
+        double m = 0.0;
+#pragma unroll
+        for (int u = 0; u < NT; ++u) m = u == kb ? Mr[u][v] : m;
+        if (tx + 16 * v < n) row[tx + 16 * v] = m;
+      }
+    }
+    __syncthreads();
+    const double piv = row[k];
     if (!(piv > 1e-300)) {
       if (threadIdx.x == 0) singular = 1;
       break;
     }
     const double ip = 1.0 / piv;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) colk[i] = M[i * n + k];
-    __syncthreads();
-    for (int j = threadIdx.x; j < n; j += blockDim.x) M[k * n + j] = (j == k ? 1.0 : M[k * n + j]) * ip;
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int i = e / n, j = e - i * n;
-      if (i == k) continue;
-      const double base = (j == k) ? 0.0 : M[e];
-      M[e] = base - colk[i] * M[k * n + j];
+    double rk[NT];                                       // row k, scaled
+#pragma unroll
+    for (int v = 0; v < NT; ++v) {
+      const int q = tx + 16 * v;
+      rk[v] = (q == k ? 1.0 : row[q < n ? q : n - 1]) * ip;
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int p = ty + 16 * u;
+      const double cp = col[p < n ? p : n - 1];
+#pragma unroll
+      for (int v = 0; v < NT; ++v) {
+        const int q = tx + 16 * v;
+        const double e = (q == k ? 0.0 : Mr[u][v]) - cp * rk[v];
+        Mr[u][v] = p == k ? rk[v] : e;
+      }
+    }
   }
   __syncthreads();
   if (singular && threadIdx.x == 0) atomicOr(a.flags, 2);
   double* out = a.Minv + (size_t)slot * a.minv_step + w.minv_off;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) out[e] = M[e];
+#pragma unroll
+  for (int u = 0; u < NT; ++u)
+#pragma unroll
+    for (int v = 0; v < NT; ++v) {
+      const int p = ty + 16 * u, q = tx + 16 * v;
+      if (p < n && q < n) out[(size_t)p * n + q] = Mr[u][v];
+    }
 }
 
+template <int NT>
 __global__ void __launch_bounds__(256) k_factor(Group gr) {
   int lb;
   const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
-  factor_block(*a, lb);
+  factor_block<NT>(*a, lb);
 }
 
 // rho and u* = (sum c f + F_body/2)/rho (Eqs. 2, 9, 11) of the
@@ -520,14 +575,24 @@ hipError_t launch_factor(const MarkerArgs* const* host, const void* const* dev, 
     }
     blocks[j] = count * a.nw;
   }
-  const size_t lds = ((size_t)maxnp * maxnp + (size_t)(kPw + 1) * maxnp) * sizeof(double) +
-                     (size_t)maxmask * sizeof(unsigned);
-  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_factor), lds);
+  const size_t lds = (size_t)(kPw + 4) * maxnp * sizeof(double) + (size_t)maxmask * sizeof(unsigned);
+  // register tile of the elimination: the smallest NT with 16 NT >= n_p
+  const int nt = maxnp <= 32 ? 2 : (maxnp <= 64 ? 4 : (maxnp <= 96 ? 6 : 8));
+  const void* fn = nt == 2   ? reinterpret_cast<const void*>(k_factor<2>)
+                   : nt == 4 ? reinterpret_cast<const void*>(k_factor<4>)
+                   : nt == 6 ? reinterpret_cast<const void*>(k_factor<6>)
+                             : reinterpret_cast<const void*>(k_factor<8>);
+  hipError_t e = raise_lds(fn, lds);
   if (e != hipSuccess) return e;
   Group g;
   const int total = group_fill(g, dev, blocks, n);
   if (total == 0) return hipSuccess;
-  k_factor<<<(unsigned)total, 256, lds, s>>>(g);
+  switch (nt) {
+    case 2: k_factor<2><<<(unsigned)total, 256, lds, s>>>(g); break;
+    case 4: k_factor<4><<<(unsigned)total, 256, lds, s>>>(g); break;
+    case 6: k_factor<6><<<(unsigned)total, 256, lds, s>>>(g); break;
+    default: k_factor<8><<<(unsigned)total, 256, lds, s>>>(g); break;
+  }
   return hipGetLastError();
 }
 
