@@ -222,7 +222,8 @@ IBMLBM_API int64_t ibmlbm_step_count(ibmlbm_t h);
  *   CM          Mz over 0.5 u_ref^2 area_ref chord.
  * Synchronises the stream.  ERANGE if a row is not in the ring, ESTATE with
  * no foils, EDIVERGED if a check step saw a non-finite density or a perimeter
- * system became singular (the rows are still copied). */
+ * system became singular, EDEVICE if a foil's support nodes outnumbered the
+ * band-moment grid the host sized for them (the rows are still copied). */
 IBMLBM_API int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out);
 
 /* Copy a field of the current state to host float64 (caller-owned, x

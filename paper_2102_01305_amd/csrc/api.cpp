@@ -1165,6 +1165,7 @@ int ibmlbm_forces(ibmlbm_t h, int64_t first, int64_t count, double* out) {
     HIP_TRY(h, hipMemcpy(out + k * row, hist + r * row, (size_t)run * row * 8, hipMemcpyDeviceToHost));
     k += run;
   }
+  if (flags & 4) return fail(h, IBMLBM_EDEVICE, "a foil's support nodes outnumbered the band grid sized for them");
   if (flags & 2) return fail(h, IBMLBM_EDIVERGED, "a perimeter system became singular");
   if (flags & 1) return fail(h, IBMLBM_EDIVERGED, "non-finite density seen on a check step");
   return IBMLBM_OK;

@@ -128,7 +128,11 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
           *e++ = ((unsigned)r << 16) | (unsigned)(q * 32 + bit);
         }
       }
-      if (r == rows - 1) out[0] = (unsigned)(o + rc[r]);
+      if (r == rows - 1) {
+        out[0] = (unsigned)(o + rc[r]);
+        // the band grid of that step covers sup_chunks * 64 entries
+        if (o + rc[r] > 64 * ws.sup_chunks) atomicOr(a.flags, 4);
+      }
     }
     __syncthreads();
   }

@@ -124,5 +124,5 @@ def test_large_config_properties():
     sym_y = np.abs(h[:, 0, 1] + h[:, 1, 1]).max() / scale
     e16 = l2rel(runs["fp16"][1], u32)
     print(f"[large] mirror Fx {sym_x:.2e} Fy {sym_y:.2e}; fp16 vs fp32 L2 rel u {e16:.2e}", flush=True)
-    assert sym_x <= 1e-4 and sym_y <= 1e-4
+    assert sym_x <= 1e-6 and sym_y <= 1e-6   # FP32 rounding: measured about 1e-8
     assert e16 <= 1e-3
