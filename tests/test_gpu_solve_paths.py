@@ -5,7 +5,9 @@
   then runs with 256 threads and two parts of the span range (up to about
   330 layers it runs 512 threads and eight parts);
 * chord 40: 84 perimeter markers per layer, so the 84 x 84 perimeter
-  inverse, its window of factors and the layer kernel's larger node box.
+  inverse, its window of factors and the layer kernel's larger node box;
+* chord 48: over 96 perimeter markers, the largest register tile of the
+  perimeter factor and the inverse read from L2 by the layer kernel.
 
 Both cases compare u (global L2 and element-wise on the marker supports),
 every force/moment column per step and the marker quantities of the last
@@ -83,4 +85,21 @@ def test_chord_40_perimeter():
     gpu, ora = _run(case, t0, 20)
     assert gpu.markers("dA").size == 2 * 84 * 16
     _check(gpu, ora, t0, 20)
+    gpu.close()
+
+
+def test_chord_48_perimeter():
+    """Chord 48: about 101 perimeter markers per layer, past 96, so the
+    perimeter factor holds its block in the largest register tile (8 x 8
+    entries per thread) and the layer kernel reads the inverse from L2."""
+    case = dict(seed=11, nx=160, ny=144, nz=8, chord=48.0, re=150.0, j=0.01, f=0.25)
+    from oracle import params
+    bx, wg, ph, _ = clap_fling(**case)
+    T = params.complete_case(bx, wg, ph)[1][0]["period_steps"]
+    t0 = int(T / 8)
+    _say("clap & fling 160x144x8, c=48 (over 96 perimeter markers), 12 steps from step", t0)
+    gpu, ora = _run(case, t0, 12)
+    n_p = gpu.markers("dA").size // (2 * 8)
+    assert 96 < n_p <= 128, n_p
+    _check(gpu, ora, t0, 12)
     gpu.close()
