@@ -248,8 +248,12 @@ __device__ __forceinline__ void band_block(const MarkerArgs& __restrict__ a, int
   const int z = R / w.sup_chunks, chunk = R - z * w.sup_chunks;
   const auto* list = gmem(a.sup + (size_t)a.slot * a.sup_step + w.sup_off);
   const int e = chunk * 64 + lane;
-  if (e >= (int)list[0]) return;
-  const unsigned cell = list[1 + e];
+  // the count and the lane's entry are loaded together (the entry index
+  // kept inside the list's 16 n_p entries), then the lane checks the count
+  const int last = 16 * w.np;
+  const unsigned cnt = list[0];
+  const unsigned cell = list[1 + (e < last ? e : last - 1)];
+  if (e >= (int)cnt) return;
   const int lx = (int)(cell & 0xffffu), ly = (int)(cell >> 16);
   float f[kQ];
   pull19<St>(static_cast<const T*>(a.src), a.g, w.x0 + lx, w.y0 + ly, z, f);
@@ -332,15 +336,20 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
   double* Bc = G + 2 * ns;      // 3 * ns
   double* Pa = Bc + 3 * ns;     // parts * 3 * ns partial sums
   double* R = Pa + (size_t)parts * 3 * ns;                              // 4 * ns
-  double* r = R + 4 * ns;                                               // kPw
   const auto* Gg = gmem(a.G + w.g_off);
   for (int i = threadIdx.x; i < ns; i += bd) {
     const double g = Gg[i];
     G[i] = g;
     G[i + ns] = g;
   }
-  copy_to_lds(r, a.pw + (size_t)a.slot * a.pw_step + w.pw_off + (size_t)p * kPw, kPw);
-  __syncthreads();
+  // the marker's record, read by every thread (one address per block), so
+  // the band-record loads below wait on it and on nothing else
+  double r[kPw];
+  {
+    const auto* rg = gmem(a.pw + (size_t)a.slot * a.pw_step + w.pw_off + (size_t)p * kPw);
+#pragma unroll
+    for (int k = 0; k < kPw; ++k) r[k] = rg[k];
+  }
   const double thd = a.pose[wi][1], vx = a.pose[wi][4], vy = a.pose[wi][5];
   const double Ux = vx - thd * r[3], Uy = vy + thd * r[2];
   {
