@@ -543,9 +543,9 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
   }
   // local memory of the marker kernels: the perimeter factor block holds the
   // records, the pivot column and row (the matrix itself is in registers)
-  // and the support bitmap; the layer block holds the inverse, the records,
-  // the layer's solution, at least one partial spread image of the largest
-  // node box and an 8 KB reduction array (markers.hip)
+  // and the support bitmap; the layer block holds the records, the layer's
+  // solution, at least one partial spread image of the largest node box and
+  // an 8 KB reduction array (markers.hip)
   int maxnp = 0, maxcells = 0;
   for (int k = 0; k < nw; ++k) {
     maxnp = std::max(maxnp, geo[k].np);
@@ -554,8 +554,7 @@ int check_wings(const ibmlbm_config& c, int nw, const ibmlbm_wing* w, std::vecto
   int maxside = 0;
   for (int k = 0; k < nw; ++k) maxside = std::max(maxside, geo[k].side);
   const size_t lds_factor = (size_t)(kPwStride + 4) * maxnp * 8 + (size_t)maxside * ((maxside + 31) / 32 + 1) * 4;
-  const size_t lds_layer = ((size_t)maxnp * maxnp + (size_t)(kPwStride + 6) * maxnp) * 8 + 8192 +
-                           (size_t)maxcells * 12;
+  const size_t lds_layer = (size_t)(kPwStride + 6) * maxnp * 8 + 8192 + (size_t)maxcells * 12;
   if (nw > 0 && std::max(lds_factor, lds_layer) > kMaxLds) {
     snprintf(b, sizeof b,
              "%d perimeter markers with a node box of up to %d cells need %zu bytes of the layer kernel's "
@@ -739,19 +738,13 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   }
   ma.band_cells = (int)cells;
   ma.band_blocks = (int)((band_waves + 3) / 4);
-  // Layer kernel LDS: the perimeter inverse (staged where two blocks with
-  // one spread image still fit a compute unit, else read from L2), the
-  // records and the layer's solution, an 8 KiB reduction array, and as many
-  // partial spread images (up to 4) as fit in the budget: two blocks per
-  // compute unit with the inverse staged, three with it read from L2, else
-  // as many as fit.
-  const size_t inv = (size_t)maxnp * maxnp * 8;
-  const size_t rest = (size_t)(kPwStride + 6) * maxnp * 8 + 8192;
+  // Layer kernel LDS: the records and the layer's solution, an 8 KiB
+  // reduction array, and as many partial spread images (up to 4) as fit in
+  // the budget: three blocks per compute unit where one image allows it,
+  // else two, else as many as fit.
+  const size_t fixed = (size_t)(kPwStride + 6) * maxnp * 8 + 8192;
   const size_t per = (size_t)maxcells * 12;
-  ma.minv_global = inv + rest + per > 80 * 1024;
-  const size_t fixed = ma.minv_global ? rest : inv + rest;
-  size_t budget = 80 * 1024;
-  if (ma.minv_global) budget = fixed + per <= 53 * 1024 ? 53 * 1024 : (fixed + per <= 80 * 1024 ? 80 * 1024 : 150 * 1024);
+  const size_t budget = fixed + per <= 53 * 1024 ? 53 * 1024 : (fixed + per <= 80 * 1024 ? 80 * 1024 : 150 * 1024);
   ma.copies = 4;
   while (ma.copies > 1 && fixed + ma.copies * per > budget) --ma.copies;
 }

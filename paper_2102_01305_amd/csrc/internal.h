@@ -134,7 +134,6 @@ struct MarkerArgs {
   double* rhoB;              // 1 per marker
   double* duB;               // 3 per marker
   int copies;                // partial spread images per layer block (1..4)
-  int minv_global;           // the layer kernel reads the perimeter inverse from L2, not LDS
   int* flags;                // bit 1: singular perimeter system; bit 2: a support list longer than its bound
 };
 

@@ -462,12 +462,8 @@ __global__ void __launch_bounds__(512) k_interp_span(Group gr) {
 // without the span factor, which the collide kernel applies).  The image is
 // built in `a.copies` partial images, each added by one wave over the
 // markers p = copy (mod copies) in order, then summed copy by copy, so the
-// sums are the same on every run.
-// MG: the perimeter inverse is read from global memory (L2) instead of
-// being staged in LDS, for large perimeters whose inverse would leave room
-// for only one block per compute unit; the products are summed in the same
-// order either way.
-template <bool MG>
+// sums are the same on every run.  The perimeter inverse is read from L2
+// (measured faster than staging it in LDS, also where it fits).
 __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
   __shared__ double red[4][256];
@@ -476,15 +472,13 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
   const WingDev& w = a.w[wi];
   const int n = w.np, ns = w.ns, cells = w.bw * w.bh, copies = a.copies;
   const double* Minv_g = a.Minv + (size_t)a.slot * a.minv_step + w.minv_off;
-  double* Mi = lds;                                  // n * n (LDS form)
-  double* P = MG ? lds : Mi + n * n;                 // n * kPw
+  double* P = lds;                                   // n * kPw
   double* Tl = P + n * kPw;                          // n * 3
   double* Y = Tl + 3 * n;                            // n * 3
   float* img = reinterpret_cast<float*>(Y + 3 * n);  // copies * cells * 3
   // rho_B of this thread's first marker, fetched while the block loads
   const int p0 = (int)threadIdx.x;
   const double rho_p0 = p0 < n ? gmem(a.rhoB)[(size_t)w.moff + (size_t)p0 * ns + s] : 0.0;
-  if (!MG) copy_to_lds(Mi, Minv_g, n * n);
   copy_to_lds(P, a.pw + (size_t)a.slot * a.pw_step + w.pw_off, n * kPw);
   copy_to_lds(Tl, a.T + w.c_off + (size_t)s * n * 3, 3 * n);
   for (int i = threadIdx.x; i < copies * 3 * cells; i += blockDim.x) img[i] = 0.f;
@@ -493,21 +487,13 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
     const int p = e / 3, c = e - 3 * p;
     double y0 = 0.0, y1 = 0.0;
     int q = 0;
-    if (MG) {
-      const auto* row = gmem(Minv_g + (size_t)p * n);
+    const auto* row = gmem(Minv_g + (size_t)p * n);
 #pragma unroll 6
-      for (; q + 1 < n; q += 2) {
-        y0 += row[q] * Tl[3 * q + c];
-        y1 += row[q + 1] * Tl[3 * (q + 1) + c];
-      }
-      if (q < n) y0 += row[q] * Tl[3 * q + c];
-    } else {
-      for (; q + 1 < n; q += 2) {
-        y0 += Mi[p * n + q] * Tl[3 * q + c];
-        y1 += Mi[p * n + q + 1] * Tl[3 * (q + 1) + c];
-      }
-      if (q < n) y0 += Mi[p * n + q] * Tl[3 * q + c];
+    for (; q + 1 < n; q += 2) {
+      y0 += row[q] * Tl[3 * q + c];
+      y1 += row[q + 1] * Tl[3 * (q + 1) + c];
     }
+    if (q < n) y0 += row[q] * Tl[3 * q + c];
     Y[e] = y0 + y1;
   }
   __syncthreads();
@@ -561,11 +547,10 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
   }
 }
 
-template <bool MG>
 __global__ void __launch_bounds__(256) k_layer(Group gr) {
   int lb;
   const MarkerArgs* a = static_cast<const MarkerArgs*>(group_find(gr, lb));
-  layer_block<MG>(*a, lb);
+  layer_block(*a, lb);
 }
 
 size_t marker_span_lds(int ns) { return interp_span_lds(ns); }
@@ -614,8 +599,6 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
   if (n < 1 || n > kMaxGroup) return hipErrorInvalidValue;
   int nb[kMaxGroup], nl[kMaxGroup], np[kMaxGroup];
   size_t lds_l = 0, lds_s = 0;
-  bool mg = false;   // a solve of the group reads its inverse from L2
-  for (int j = 0; j < n; ++j) mg = mg || host[j]->minv_global;
   for (int j = 0; j < n; ++j) {
     const MarkerArgs& a = *host[j];
     int maxnp = 0, layers = 0, perims = 0, maxcells = 0;
@@ -626,8 +609,7 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
       const int c = a.w[k].bw * a.w[k].bh;
       maxcells = c > maxcells ? c : maxcells;
     }
-    const size_t ll = ((mg ? 0 : (size_t)maxnp * maxnp) + (size_t)(kPw + 6) * maxnp) * sizeof(double) +
-                      (size_t)a.copies * maxcells * 3 * sizeof(float);
+    const size_t ll = (size_t)(kPw + 6) * maxnp * sizeof(double) + (size_t)a.copies * maxcells * 3 * sizeof(float);
     lds_l = ll > lds_l ? ll : lds_l;
     nb[j] = a.band_blocks;   // 4 box rows per block
     nl[j] = layers;
@@ -640,8 +622,7 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
     const size_t ls = interp_span_lds(host[j]->g.nz);
     lds_s = ls > lds_s ? ls : lds_s;
   }
-  hipError_t e = raise_lds(mg ? reinterpret_cast<const void*>(k_layer<true>)
-                              : reinterpret_cast<const void*>(k_layer<false>), lds_l);
+  hipError_t e = raise_lds(reinterpret_cast<const void*>(k_layer), lds_l);
   if (e == hipSuccess) e = raise_lds(reinterpret_cast<const void*>(k_interp_span), lds_s);
   if (e != hipSuccess) return e;
   Group g;
@@ -661,10 +642,7 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   total = group_fill(g, dev, nl, n);
-  if (mg)
-    k_layer<true><<<total, 256, lds_l, s>>>(g);
-  else
-    k_layer<false><<<total, 256, lds_l, s>>>(g);
+  k_layer<<<total, 256, lds_l, s>>>(g);
   return hipGetLastError();
 }
 

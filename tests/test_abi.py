@@ -145,13 +145,14 @@ def test_plate_and_figure_eight_params():
     assert lib.ibmlbm_figure_eight_params(75.0, 0.05, 15.0, -1.0, C.byref(t), None) == L.EINVAL
 
 
-@pytest.mark.parametrize("chord,accepted", [(50.0, True), (60.0, False)])
+@pytest.mark.parametrize("chord,accepted", [(50.0, True), (60.0, True), (62.0, False)])
 def test_marker_local_memory_limit(chord, accepted):
-    """The layer kernel keeps the perimeter inverse (n_p^2 doubles) and a
-    partial spread image of the foil's node box in local memory: a clap &
-    fling pair at aspect ratio 5 with chord 50 (105 perimeter markers) fits
-    the 160 KB of a workgroup, chord 60 (126 markers) does not and is
-    refused at configuration time, not at the first step."""
+    """The marker kernels keep the perimeter records, a pivot row and column
+    and the spread images in local memory (the perimeter block itself in
+    registers, its inverse in L2), so a foil of up to the 128 perimeter
+    markers a foil may have fits the 160 KB of a workgroup: a clap & fling
+    pair at aspect ratio 5 with chord 60 (126 markers) is accepted, chord 62
+    (130 markers) is refused at configuration time, not at the first step."""
     L, lib = _lib()
     from paper_2102_01305_amd.solver import complete_case, make_wings
     bx, wg, ph = WL.clap_fling_case(nx=400, ny=320, nz=8, chord=chord, re=100.0, j=0.01, f=0.25)
@@ -161,7 +162,7 @@ def test_marker_local_memory_limit(chord, accepted):
         assert n > 0
     else:
         assert n == 0
-        assert b"local memory" in lib.ibmlbm_last_error(None)
+        assert b"perimeter markers" in lib.ibmlbm_last_error(None)
 
 
 def test_solver_refuses_without_gpu():

@@ -7,7 +7,7 @@
 * chord 40: 84 perimeter markers per layer, so the 84 x 84 perimeter
   inverse, its window of factors and the layer kernel's larger node box;
 * chord 48: over 96 perimeter markers, the largest register tile of the
-  perimeter factor and the inverse read from L2 by the layer kernel.
+  perimeter factor.
 
 Both cases compare u (global L2 and element-wise on the marker supports),
 every force/moment column per step and the marker quantities of the last
@@ -91,7 +91,7 @@ def test_chord_40_perimeter():
 def test_chord_48_perimeter():
     """Chord 48: about 101 perimeter markers per layer, past 96, so the
     perimeter factor holds its block in the largest register tile (8 x 8
-    entries per thread) and the layer kernel reads the inverse from L2."""
+    entries per thread)."""
     case = dict(seed=11, nx=160, ny=144, nz=8, chord=48.0, re=150.0, j=0.01, f=0.25)
     from oracle import params
     bx, wg, ph, _ = clap_fling(**case)
