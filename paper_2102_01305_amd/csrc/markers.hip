@@ -410,34 +410,34 @@ __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__
     }
   }
   __syncthreads();
-  // items (part, four outputs s0 = 4 t) in turns of the block
-  for (int item = threadIdx.x; item < parts * groups; item += bd) {
-    const int part = item / groups, t = item - part * groups;
+  // items (part, four outputs t + j Q, j = 0..3, Q = ceil(ns / 4)) in turns
+  // of the block: neighbouring threads read neighbouring G entries (no LDS
+  // bank conflicts); each output sums its part of the s2 range in order
+  const int Q = groups;
+  for (int item = threadIdx.x; item < parts * Q; item += bd) {
+    const int part = item / Q, t = item - part * Q;
     const int lo = part * ns / parts, hi = (part + 1) * ns / parts;
-    {
-      const int s0 = 4 * t;
-      double acc[4][3];
+    double acc[4][3];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
-      // output s0 + j takes G[(s0 + j - s2) mod ns]
-      double g0 = G[(s0 - lo + ns) % ns], g1 = G[(s0 + 1 - lo + ns) % ns],
-             g2 = G[(s0 + 2 - lo + ns) % ns], g3 = G[(s0 + 3 - lo + ns) % ns];
+    for (int j = 0; j < 4; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0;
+    // output t + j Q takes G[(t + j Q - s2) mod ns] = G[t + j Q - s2 + ns]
+    const double* G0 = G + t + ns;
 #pragma unroll 4
-      for (int s2 = lo; s2 < hi; ++s2) {
-        const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
-        acc[0][0] += g0 * b0; acc[0][1] += g0 * b1; acc[0][2] += g0 * b2;
-        acc[1][0] += g1 * b0; acc[1][1] += g1 * b1; acc[1][2] += g1 * b2;
-        acc[2][0] += g2 * b0; acc[2][1] += g2 * b1; acc[2][2] += g2 * b2;
-        acc[3][0] += g3 * b0; acc[3][1] += g3 * b1; acc[3][2] += g3 * b2;
-        // slide to s2 + 1: output s0 + j then takes the old window value j - 1
-        g3 = g2;
-        g2 = g1;
-        g1 = g0;
-        g0 = G[s0 - s2 - 1 + ns];   // index in [s0, s0 + ns - 1]
+    for (int s2 = lo; s2 < hi; ++s2) {
+      const double b0 = Bc[s2], b1 = Bc[ns + s2], b2 = Bc[2 * ns + s2];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double g = G0[j * Q - s2];
+        acc[j][0] += g * b0;
+        acc[j][1] += g * b1;
+        acc[j][2] += g * b2;
       }
-      const int cnt = ns - s0 < 4 ? ns - s0 : 4;
-      for (int j = 0; j < cnt; ++j)
-        for (int c = 0; c < 3; ++c) Pa[((size_t)part * ns + s0 + j) * 3 + c] = acc[j][c];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int so = t + j * Q;
+      if (so < ns)
+        for (int c = 0; c < 3; ++c) Pa[((size_t)part * ns + so) * 3 + c] = acc[j][c];
     }
   }
   __syncthreads();
