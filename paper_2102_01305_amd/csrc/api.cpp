@@ -13,6 +13,7 @@
 
 #include "divmul.h"
 #include "internal.h"
+#include "marker_args.h"
 #include "kinematics.h"
 
 using namespace ibmk;

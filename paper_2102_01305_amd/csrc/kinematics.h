@@ -5,7 +5,7 @@
 
 #include <cmath>
 
-#include "internal.h"
+#include "marker_args.h"
 
 namespace ibmk {
 
