@@ -722,7 +722,7 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
   }
   ma.src = ca.src;
   ca.hist_row = s % c.history_steps;
-  long long cells = 0, band_waves = 0;
+  long long band_waves = 0;
   int maxnp = 0, maxcells = 0;
   for (int w = 0; w < h->nw; ++w) {
     node_box(h->wings[w], h->geom[w], (double)s, c, ma.w[w]);
@@ -731,13 +731,11 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     b.side = ma.w[w].side;
     b.band = ma.w[w].band;
     b.corr = ma.w[w].corr;
-    cells += (long long)b.w * b.h * c.nz;
     ma.w[w].sup_chunks = (support_bound(h->wings[w], h->geom[w], (double)s, ma.w[w]) + 63) / 64;
     band_waves += (long long)ma.w[w].sup_chunks * c.nz;
     maxnp = std::max(maxnp, ma.w[w].np);
     maxcells = std::max(maxcells, ma.w[w].bw * ma.w[w].bh);
   }
-  ma.band_cells = (int)cells;
   ma.band_blocks = (int)((band_waves + 3) / 4);
   // Layer kernel LDS: the records and the layer's solution, an 8 KiB
   // reduction array, and as many partial spread images (up to 4) as fit in

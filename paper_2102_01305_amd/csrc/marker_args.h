@@ -31,7 +31,6 @@ struct MarkerArgs {
   Phys p;
   int nw;
   int m_total;
-  int band_cells;            // sum over foils of bw*bh*nz
   int band_blocks;           // blocks of 4 band waves (64 support cells of one foil's layer each)
   WingDev w[kMaxWings];
   double wz[4];              // span weights of a node at offsets -1.5, -0.5, 0.5, 1.5

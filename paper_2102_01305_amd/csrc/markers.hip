@@ -290,9 +290,10 @@ __device__ __forceinline__ int find_layer_block(const MarkerArgs& a, int blk, in
 //    I u* at the marker on layer s are sum_k wz_k R(s - 1 + k), k = 0..3
 //    (Eq. 17); B = U_B - I u* (Eq. 19).
 //  * T(p, c, s) = sum_s2 G[(s - s2) mod ns] B(p, c, s2), G the pseudo-inverse
-//    row of the circulant span factor: each thread makes four consecutive
-//    outputs from a sliding window of G over one part of the s2 range; the
-//    parts are added in a fixed order.  T is written layer-major.
+//    row of the circulant span factor: each item of the block makes the four
+//    outputs t, t + Q, t + 2Q, t + 3Q (Q = ceil(ns / 4)) over one part of the
+//    s2 range; the parts are added in a fixed order.  T is written
+//    layer-major.
 // One block holds every layer of its marker, so B never leaves the block.
 __host__ __device__ inline int parts_at(int ns, int threads) {
   const int groups = (ns + 3) / 4;                   // threads per part
@@ -300,10 +301,10 @@ __host__ __device__ inline int parts_at(int ns, int threads) {
   return parts < 1 ? 1 : (parts > 8 ? 8 : parts);
 }
 
-// LDS of a block: G (2 ns), B (3 ns), partial sums (parts x 3 ns), the xy
-// sums R (4 ns) and the marker's record.
+// LDS of a block: G (2 ns), B (3 ns), partial sums (parts x 3 ns) and the
+// xy sums R (4 ns).
 __host__ __device__ inline size_t interp_span_doubles(int ns, int parts) {
-  const size_t d = (size_t)(9 + 3 * parts) * ns + kPw;
+  const size_t d = (size_t)(9 + 3 * parts) * ns;
   return (d + 1) / 2 * 2;
 }
 __host__ __device__ inline size_t lds_at(int ns, int threads) {
@@ -611,7 +612,7 @@ hipError_t launch_markers(int storage, const MarkerArgs* const* host, const void
     }
     const size_t ll = (size_t)(kPw + 6) * maxnp * sizeof(double) + (size_t)a.copies * maxcells * 3 * sizeof(float);
     lds_l = ll > lds_l ? ll : lds_l;
-    nb[j] = a.band_blocks;   // 4 box rows per block
+    nb[j] = a.band_blocks;   // 4 waves per block, 64 support-list entries per wave
     nl[j] = layers;
     np[j] = perims;
   }
