@@ -29,6 +29,7 @@ import numpy as np
 from .solver import Solver, step_batch, workspace_bytes
 
 MAX_BATCH = 64       # solves per grouped launch (the library's limit)
+PREFETCH_BYTES = 4 << 30   # host memory for initial fields made ahead of admission
 
 
 @dataclasses.dataclass
@@ -86,16 +87,19 @@ class GpuBackend:
         self.torch = torch
         self.compute = torch.cuda.current_stream(self.device)
         self.side = torch.cuda.Stream(self.device)
+        self._fp = {}   # footprints by request id, handed on to create()
 
     def free_bytes(self):
         return self.torch.cuda.mem_get_info(self.device)[0]
 
     def footprint(self, req: SweepRequest) -> int:
-        return workspace_bytes(req.box, req.wings, req.storage, history_steps=max(req.steps, 1))
+        fp = workspace_bytes(req.box, req.wings, req.storage, history_steps=max(req.steps, 1))
+        self._fp[req.rid] = fp
+        return fp
 
     def create(self, req: SweepRequest, u0=None):
         s = Solver(req.box, req.wings, storage=req.storage, history_steps=max(req.steps, 1),
-                   device=self.device, stream=self.side)
+                   device=self.device, stream=self.side, nbytes=self._fp.pop(req.rid, None) or None)
         if u0 is None:
             u0 = req.u0() if callable(req.u0) else req.u0
         s.init_fields(u=u0)
@@ -143,14 +147,22 @@ class SweepServer:
         def now():
             return time.perf_counter() - t0
 
-        pool = concurrent.futures.ThreadPoolExecutor(max_workers=2)
+        pool = concurrent.futures.ThreadPoolExecutor(max_workers=4)
         prepared = {}
 
         def prefetch():
-            # make the initial fields of the next few waiting requests on
-            # host threads while the device works
-            for r in list(waiting)[:4]:
-                if callable(r.u0) and r.rid not in prepared:
+            # make the initial fields of the waiting requests that the next
+            # admissions can take (up to a batch, within PREFETCH_BYTES of
+            # host memory) on host threads while the device works, so that
+            # admitting a batch does not wait for them
+            held = 0
+            for r in list(waiting)[:self.max_batch]:
+                if not callable(r.u0):
+                    continue
+                held += 24 * r.box["nx"] * r.box["ny"] * r.box["nz"]   # 3 FP64 components
+                if held > PREFETCH_BYTES:
+                    break
+                if r.rid not in prepared:
                     prepared[r.rid] = pool.submit(r.u0)
 
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))

@@ -109,7 +109,7 @@ class Solver:
     """One D3Q19 + IBM solve on one GPU (one handle, one workspace)."""
 
     def __init__(self, bx, wings=(), storage="fp32", check_interval=0, history_steps=1024,
-                 device=None, stream=None, noalloc=False):
+                 device=None, stream=None, noalloc=False, nbytes=None):
         import torch
 
         if not torch.cuda.is_available():
@@ -125,7 +125,10 @@ class Solver:
         # noalloc: the buffer holds the two lattice states only (the lattice
         # part of the workspace is an upper bound) and the library keeps every
         # other region in its static device scratch (ibmlbm_create_noalloc)
-        nbytes = self.lib.ibmlbm_workspace_bytes(C.byref(self.cfg), 0 if noalloc else nw, self._wings)
+        # nbytes: a workspace size the caller already has from
+        # workspace_bytes() for the same description (create checks it)
+        if nbytes is None or noalloc:
+            nbytes = self.lib.ibmlbm_workspace_bytes(C.byref(self.cfg), 0 if noalloc else nw, self._wings)
         if nbytes == 0:
             raise L.IbmlbmError(L.EINVAL, self.lib.ibmlbm_last_error(None).decode())
         self.nbytes = int(nbytes)
