@@ -38,6 +38,7 @@ class FakeBackend:
 
     def create(self, req, u0=None):
         self.admitted.append(req.rid)
+        self.u0s = getattr(self, "u0s", []) + [u0]
         return FakeSolver(req)
 
     def step(self, solvers, n):
@@ -117,3 +118,31 @@ def test_summary_percentiles_and_rate():
     assert s["p50_s"] == pytest.approx(float(np.percentile(lat, 50)))
     assert s["p99_s"] == pytest.approx(float(np.percentile(lat, 99)))
     assert s["mlups"] > 0
+
+
+def test_initial_fields_made_ahead_within_the_host_bound(monkeypatch):
+    """The fields of waiting requests are made on host threads before their
+    admission, as far as PREFETCH_BYTES of host memory allows; a request past
+    that bound is handed no field (its backend makes it at admission)."""
+    from paper_2102_01305_amd import serve
+
+    made = []
+
+    def field(rid):
+        def make():
+            made.append(rid)
+            return np.full((3, 4, 4, 4), float(rid))
+        return make
+
+    # room for two 4 x 4 x 4 fields of 3 FP64 components
+    monkeypatch.setattr(serve, "PREFETCH_BYTES", 2 * 24 * 64)
+    be = FakeBackend()
+    srv = SweepServer(hbm_budget=100, chunk=10, max_batch=6, backend=be)
+    reqs = [SweepRequest(rid=i, box=dict(nx=4, ny=4, nz=4, bytes=1), wings=[{}], steps=10, u0=field(i))
+            for i in range(6)]
+    res = srv.run(reqs)
+    assert all(r.error is None for r in res)
+    assert be.admitted == list(range(6))
+    got = [None if u is None else int(u[0, 0, 0, 0]) for u in be.u0s]
+    assert got == [0, 1, None, None, None, None]
+    assert sorted(made) == [0, 1]
