@@ -213,3 +213,21 @@ def test_span_longer_than_the_marker_block_is_rejected():
     assert 1024 <= top < 4096
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top))), 1, make_wings(wg)) > 0
     assert lib.ibmlbm_workspace_bytes(C.byref(_cfg(dict(bx, nz=top + 1))), 1, make_wings(wg)) == 0
+
+
+@pytest.mark.parametrize("ds,accepted", [(1.0, True), (0.5, True), (0.3, False)])
+def test_crowded_perimeter_is_refused_as_singular(ds, accepted):
+    """Markers much closer than the lattice spacing make the perimeter block
+    of the no-slip matrix (Eq. 18) singular in floating point: the plate foil
+    (chord 10, thickness 2) with marker spacing 1 or 0.5 is accepted, with
+    0.3 it is refused at configuration time with the reason."""
+    L, lib = _lib()
+    from paper_2102_01305_amd.solver import make_wings
+    bx, wg = _plate()
+    w = [dict(wg[0], ds=ds)]
+    n = lib.ibmlbm_workspace_bytes(C.byref(_cfg(bx)), 1, make_wings(w))
+    if accepted:
+        assert n > 0
+    else:
+        assert n == 0
+        assert b"singular" in lib.ibmlbm_last_error(None)
