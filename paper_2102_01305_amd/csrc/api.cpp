@@ -586,7 +586,7 @@ MarkerLayout marker_layout(const ibmlbm_config& c, int nw, const std::vector<Win
   take(M.G, nG * 8);
   take(M.Minv, (size_t)kFactorWindow * nMinv * 8);
   take(M.pw, (size_t)kFactorWindow * M.perims * kPwStride * 8);
-  for (int k = 0; k < nw; ++k) M.sup_step += 1 + 16 * geo[k].np;
+  for (int k = 0; k < nw; ++k) M.sup_step += 1 + 16 * geo[k].np + geo[k].side * ((geo[k].side + 31) / 32);
   take(M.sup, (size_t)kFactorWindow * M.sup_step * 4);
   M.minv_step = (int)nMinv;
   M.pw_step = M.perims * kPwStride;
@@ -731,6 +731,8 @@ void step_args(ibmlbm_t h, long long s, bool cur_A, CollideArgs& ca, MarkerArgs&
     b.side = ma.w[w].side;
     b.band = ma.w[w].band;
     b.corr = ma.w[w].corr;
+    b.words = ma.w[w].mask_words;
+    b.bits = ma.sup + (size_t)ma.slot * ma.sup_step + ma.w[w].sup_off + 1 + 16 * ma.w[w].np;
     ma.w[w].sup_chunks = (support_bound(h->wings[w], h->geom[w], (double)s, ma.w[w]) + 63) / 64;
     band_waves += (long long)ma.w[w].sup_chunks * c.nz;
     maxnp = std::max(maxnp, ma.w[w].np);
@@ -1102,7 +1104,7 @@ int ibmlbm_set_kinematics(ibmlbm_t h, int32_t n_wings, const ibmlbm_wing* wings)
     goff += d.ns;
     moff2 += d.np * d.np;
     pwoff += kPwStride * d.np;
-    supoff += 1 + 16 * d.np;
+    supoff += 1 + 16 * d.np + d.side * d.mask_words;
     loff += d.ns;
   }
   HIP_TRY(h, hipMemcpyAsync(h->sb + M.ref.off, ref.data(), ref.size() * 8, hipMemcpyHostToDevice, h->stream));

@@ -27,7 +27,8 @@ __device__ __forceinline__ bool in_box(const FoilBox& b, int x, int y) {
 
 // du(x) of the IBM correction (Eq. 15): the sum over foils and the 4 span
 // layers within reach of the layer images written by the spread kernel.
-// Returns whether a foil's node box covers the cell.
+// Returns whether the cell is a support node of a foil's markers (elsewhere
+// the correction is exactly zero and the images are not read).
 __device__ __forceinline__ bool correction(const CollideArgs& a, int x, int y, int z, float& dux,
                                            float& duy, float& duz) {
   const Geo& g = a.g;
@@ -38,6 +39,7 @@ __device__ __forceinline__ bool correction(const CollideArgs& a, int x, int y, i
     if (y < b.y0 || y >= b.y0 + b.h) continue;         // wave-uniform: most rows miss
     if (!in_box(b, x, y)) continue;
     const int lx = x - b.x0, ly = y - b.y0;
+    if (!((b.bits[ly * b.words + (lx >> 5)] >> (lx & 31)) & 1u)) continue;   // zero there
     hit = true;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

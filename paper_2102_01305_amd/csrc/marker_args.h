@@ -13,7 +13,7 @@ struct WingDev {
   int g_off;                 // offset of this foil's span pseudo-inverse row (ns)
   int minv_off;              // offset of this foil's perimeter inverse (np x np)
   int pw_off;                // offset of this foil's per-step perimeter records (np x 14)
-  int sup_off;               // offset of this foil's support list in a window slot (1 + np*16 words)
+  int sup_off;               // offset of this foil's support list in a window slot (1 + np*16 words, then side * mask_words of bitmap)
   int mask_words;            // 32-bit words per node-box row of the support bitmap
   int sup_chunks;            // this step's band waves per layer: 64-cell chunks of a bound on its support count
   int c_off;                 // offset of this foil's span-solved T (ns x np x 3)

@@ -116,6 +116,8 @@ __device__ __forceinline__ void factor_block(const MarkerArgs& __restrict__ a, i
     }
     __syncthreads();
     unsigned* out = a.sup + (size_t)slot * a.sup_step + w.sup_off;
+    // the bitmap itself after the list, for the collide kernel
+    for (int e = threadIdx.x; e < rows * words; e += blockDim.x) out[1 + 16 * n + e] = bits[e];
     for (int r = threadIdx.x; r < rows; r += blockDim.x) {
       int o = 0;
       for (int q = 0; q < r; ++q) o += rc[q];
