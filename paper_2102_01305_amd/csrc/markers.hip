@@ -462,10 +462,10 @@ __global__ void __launch_bounds__(512) k_interp_span(Group gr) {
 // y(p) = sum_q M_xy^-1[p][q] T(q, s), du_B = y / dA (Eqs. 18-19); the body
 // force and moment of the layer, -2 rho_B y (Eq. 26), reduced in a fixed
 // order; and the xy image of sum_p du_B D_xy dA over the foil's box (Eq. 15
-// without the span factor, which the collide kernel applies).  The image is
-// built in `a.copies` partial images, each added by one wave over the
-// markers p = copy (mod copies) in order, then summed copy by copy, so the
-// sums are the same on every run.  The perimeter inverse is read from L2
+// without the span factor, which the collide kernel applies) at the
+// support nodes of the step.  The image is built in `a.copies` partial
+// images, each added by one wave over the markers p = copy (mod copies) in
+// order, then summed copy by copy, so the sums are the same on every run.  The perimeter inverse is read from L2
 // (measured faster than staging it in LDS, also where it fits).
 __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
@@ -540,12 +540,18 @@ __device__ __forceinline__ void layer_block(const MarkerArgs& __restrict__ a, in
     __syncthreads();
   }
   if (threadIdx.x < 4) a.fpart[4 * ((size_t)w.layer_off + s) + threadIdx.x] = red[threadIdx.x][0];
+  // only the support nodes of this step are written: the collide kernel
+  // reads the image nowhere else (its support bitmap)
   float4* out = w.corr + (size_t)s * w.side * w.side;
-  for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+  const auto* list = gmem(a.sup + (size_t)a.slot * a.sup_step + w.sup_off);
+  const int cnt = (int)list[0];
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    const unsigned cell = list[1 + e];
+    const int lx = (int)(cell & 0xffffu), ly = (int)(cell >> 16);
+    const int i = ly * w.bw + lx;
     float v[3] = {0.f, 0.f, 0.f};
     for (int k = 0; k < copies; ++k)
       for (int c = 0; c < 3; ++c) v[c] += img[(size_t)k * 3 * cells + 3 * i + c];
-    const int ly = i / w.bw, lx = i - ly * w.bw;
     out[ly * w.side + lx] = make_float4(v[0], v[1], v[2], 0.f);
   }
 }
