@@ -325,7 +325,14 @@ __host__ __device__ inline size_t interp_span_lds(int ns) { return lds_at(ns, sp
 
 __device__ __forceinline__ void interp_span_block(const MarkerArgs& __restrict__ a, int lb) {
   extern __shared__ double lds[];
-  int wi = 0, p = lb;
+  // workgroups are dealt to the 8 XCDs in turn: blocks lb = 8 k + x take
+  // the run of markers x * (M / 8) + k, so neighbouring markers, which
+  // share most of their band records, read them through one L2 (a
+  // permutation of the solve's blocks; the tail keeps the plain order)
+  int tot = 0;
+  for (int k = 0; k < a.nw; ++k) tot += a.w[k].np;
+  const int per = tot >> 3;
+  int wi = 0, p = lb < 8 * per ? (lb & 7) * per + (lb >> 3) : lb;
   while (wi + 1 < a.nw && p >= a.w[wi].np) {
     p -= a.w[wi].np;
     ++wi;
