@@ -182,6 +182,7 @@ class SweepServer:
                     fp = fp_cache[r.rid] = self.footprint(r)
                 if fp == 0 or fp > self.budget:
                     waiting.popleft()
+                    prepared.pop(r.rid, None)
                     why = "invalid solve description" if fp == 0 else "larger than the HBM budget"
                     t = now()
                     results[r.rid] = SweepResult(r.rid, r.arrival, t, t, 0, 0, None, why)
