@@ -5,6 +5,10 @@ Re = 100, J = 0.01, f = 0.25, seeded initial noise.
 * Eight steps against the FP64 oracle run here on the whole box: u over all
   9.4M cells (global L2 and element-wise on the marker supports) and every
   force/moment column per step.
+* The largest workload, 512x384x384 (c = 40, 2 x 84 x 384 markers, Re 150),
+  eight steps from mid-stroke against the FP64 oracle on the whole box (its
+  C lattice), with the same bars; and its mirror symmetry and FP16/FP32
+  agreement as properties.
 * One full flapping period (1676 steps, two clap and fling events) against
   the stored FP64 reference tests/golden/clap_fling_256x192x192_period.npz,
   written by tests/golden/make_clap_fling_period.py from the oracle alone:
@@ -96,6 +100,64 @@ def test_clap_fling_full_period_against_stored_oracle(storage, bar_u, bar_c):
     dc = coeff_errors(f_g, hist_o)
     print(f"[period256] {storage} u@{at}: L2 rel {e:.3e} max {eb:.3e}; coefficients over {steps} steps {dc}",
           flush=True)
+    assert e <= bar_u
+    assert eb <= bar_u
+    assert max(dc.values()) <= bar_c
+
+
+_LORA = {}
+LARGE_STEPS, LARGE_T0 = 8, 37
+
+
+def _large_case():
+    bx, wg, ph = WL.clap_fling_case(nx=512, ny=384, nz=384, chord=40.0, re=150.0, j=0.01, f=0.25)
+    u0 = WL.velocity_noise((bx["nz"], bx["ny"], bx["nx"]), 0)
+    return bx, wg, ph, u0
+
+
+def _large_oracle():
+    """The FP64 oracle over the whole 512x384x384 box (its C lattice, about
+    3 s per step on 16 host threads, under 50 GB of host memory)."""
+    if not _LORA:
+        from oracle import params
+        from oracle.sim import Sim
+
+        bx, wg, ph, u0 = _large_case()
+        ob, ow = params.complete_case(bx, wg, ph)
+        u = u0.copy()
+        u[0] += ob["u_in"][0]
+        ora = Sim(ob, ow, u0=u, lattice="c")
+        ora.n = LARGE_T0
+        for k in range(LARGE_STEPS):
+            ora.step()
+            print(f"[large-oracle] step {LARGE_T0 + k} done", flush=True)
+        _LORA["u"] = ora.fields()[1]
+        _LORA["f"] = ora.forces()
+        _LORA["nodes"] = np.unique(np.asarray(ora.last["nodes"]).ravel())
+        del ora
+    return _LORA["u"], _LORA["f"], _LORA["nodes"]
+
+
+@pytest.mark.parametrize("storage,bar_u,bar_c", BARS)
+def test_large_config_against_oracle(storage, bar_u, bar_c):
+    """The largest workload at its full size, 512x384x384 with two c = 40
+    foils (2 x 84 x 384 markers, Re 150): 8 steps from mid-stroke against the
+    FP64 oracle on the whole box, u over all 75.5M cells (global L2 and
+    element-wise on the marker supports) and every force/moment column per
+    step, with the bars of the 256x192x192 case."""
+    _say("clap & fling 512x384x384, full size,", LARGE_STEPS, "steps from step", LARGE_T0, "against the oracle,",
+         storage)
+    bx, wg, ph, u0 = _large_case()
+    gpu = gpu_solver(bx, wg, ph, u0=u0, step0=LARGE_T0, storage=storage)
+    gpu.step(LARGE_STEPS)
+    u_g = gpu.fields("u")
+    f_g = gpu.forces(LARGE_T0, LARGE_STEPS)
+    gpu.close()
+    u_o, f_o, nodes = _large_oracle()
+    e = l2rel(u_g, u_o)
+    eb = node_box_error(u_g, u_o, nodes)
+    dc = coeff_errors(f_g, f_o)
+    print(f"[large] {storage} L2 rel u {e:.3e} node-box {eb:.3e} coefficients {dc}", flush=True)
     assert e <= bar_u
     assert eb <= bar_u
     assert max(dc.values()) <= bar_c
