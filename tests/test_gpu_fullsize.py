@@ -165,7 +165,8 @@ def test_large_config_against_oracle(storage, bar_u, bar_c):
 
 def test_large_config_properties():
     """The largest workload, 512x384x384 with two c = 40 wings (2 x 84 x 384
-    markers), too large for the oracle: properties that hold at any size.
+    markers), beside the oracle comparison above: properties that hold at
+    any size.
     Started at rest (plus the free stream) from mid-stroke, the pair stays
     mirror-symmetric, so F_x agree and F_y are opposite for the two wings at
     every step; and the FP16 run follows the FP32 run within the FP16
