@@ -56,6 +56,8 @@ struct FoilBox {
   int x0, y0, w, h;    // box origin and size for this step
   int side;            // pitch of the per-layer images
   int words;           // 32-bit words per row of `bits`
+  // per-layer images over the box, written and read at this step's support
+  // nodes only (below)
   const float4* band;  // [nz][side][side] rho, u*x, u*y, u*z
   const float4* corr;  // [nz][side][side] du_x, du_y, du_z, 0 (spread result)
   // this step's support nodes of the foil's markers, bit (lx, ly) relative
