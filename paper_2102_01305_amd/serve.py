@@ -76,7 +76,11 @@ class GpuBackend:
     """Solves on one ROCm device through libibmlbm.  A new solve is set up
     (workspace, markers, initial state) on a side stream, so the batch
     already running on the compute stream keeps the device busy meanwhile,
-    and then joins the compute stream."""
+    and then joins the compute stream.  The solves admitted together are set
+    up on several host threads (the library keeps no shared state between
+    handles, and its host-side geometry is most of a set-up)."""
+
+    parallel_create = True
 
     def __init__(self, device="cuda:0"):
         import torch
@@ -148,6 +152,8 @@ class SweepServer:
             return time.perf_counter() - t0
 
         pool = concurrent.futures.ThreadPoolExecutor(max_workers=4)
+        makers = (concurrent.futures.ThreadPoolExecutor(max_workers=4)
+                  if getattr(self.backend, "parallel_create", False) else None)
         prepared = {}
 
         def prefetch():
@@ -175,7 +181,8 @@ class SweepServer:
             # admission, in arrival order: a request waits for memory rather
             # than being overtaken by a smaller one
             nonlocal used
-            while waiting and len(active) < self.max_batch:
+            chosen = []
+            while waiting and len(active) + len(chosen) < self.max_batch:
                 r = waiting[0]
                 fp = fp_cache.get(r.rid)
                 if fp is None:
@@ -190,10 +197,21 @@ class SweepServer:
                 if used + fp > self.budget:
                     break
                 waiting.popleft()
-                fut = prepared.pop(r.rid, None)
-                s = self.backend.create(r, fut.result() if fut is not None else None)
                 used += fp
                 self.peak_bytes = max(self.peak_bytes, used)
+                chosen.append((r, fp, prepared.pop(r.rid, None)))
+            if not chosen:
+                return
+
+            def make(item):
+                r, _, fut = item
+                return self.backend.create(r, fut.result() if fut is not None else None)
+
+            # the solves admitted together are set up at once where the
+            # backend allows it, and join the batch in admission order
+            made = list(makers.map(make, chosen)) if makers is not None and len(chosen) > 1 else \
+                [make(c) for c in chosen]
+            for (r, fp, _), s in zip(chosen, made):
                 active.append(_Active(r, s, now(), fp=fp))
                 if log:
                     log(f"admit {r.rid} at {now():.3f}s ({len(active)} active, {used / 2**20:.0f} MiB)")
@@ -233,6 +251,8 @@ class SweepServer:
                     log(f"done {a.req.rid} at {now():.3f}s")
             active = keep
         pool.shutdown(wait=True)
+        if makers is not None:
+            makers.shutdown(wait=True)
         return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
