@@ -146,3 +146,29 @@ def test_initial_fields_made_ahead_within_the_host_bound(monkeypatch):
     got = [None if u is None else int(u[0, 0, 0, 0]) for u in be.u0s]
     assert got == [0, 1, None, None, None, None]
     assert sorted(made) == [0, 1]
+
+
+def test_parallel_set_up_keeps_the_schedule():
+    """A backend that sets up the solves admitted together on several host
+    threads (parallel_create) gets the same batches, in the same rounds, as
+    one that sets them up one by one, whatever order the threads finish in."""
+    import random
+
+    class Slow(FakeBackend):
+        def create(self, req, u0=None):
+            time.sleep(random.Random(req.rid).uniform(0.0, 2e-3))
+            return super().create(req, u0)
+
+    class Parallel(Slow):
+        parallel_create = True
+
+    reqs = [_req(i, 1 + i % 3, 10 + 5 * (i % 4)) for i in range(10)]
+    runs = []
+    for cls in (Slow, Parallel):
+        be = cls(step_s=2e-4)
+        srv = SweepServer(hbm_budget=8, chunk=5, max_batch=4, backend=be)
+        res = srv.run(reqs)
+        assert all(r.error is None for r in res)
+        runs.append((be.rounds, sorted(be.admitted)))
+    assert runs[0][1] == runs[1][1] == list(range(10))
+    assert runs[0][0] == runs[1][0]
